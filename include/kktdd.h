@@ -1,0 +1,143 @@
+/*
+ * kktdd.h -- C ABI of the MI355X (gfx950) two-level time-domain-decomposition KKT solver.
+ *
+ * Method: E. C. Cyr, "A 2-Level Domain Decomposition Preconditioner for KKT Systems with
+ * Heat-Equation Constraints" (DD27, arXiv 2305.04421).
+ *
+ * The library solves the KKT system of Eq. (5),
+ *     K = [[M_u, 0, J^T], [0, omega*M_z, L^T], [J, L, 0]],  unknowns (u, z, w),
+ * that backward Euler in time and the 5-point stencil in space (Eq. (2)) produce for the
+ * heat-equation-constrained control problem of Eq. (1), by flexible GMRES right-preconditioned
+ * with P = diag(M_u, omega*M_z, S_hat) (Eq. (7)), where S_hat^{-1} is approximated by the
+ * one-level RASQ time-subdomain sweeps of Eq. (13) combined multiplicatively with the
+ * Nicolaides coarse time level of Eqs. (14)-(15).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Grid: nx, ny are grid INTERVALS on (0,Lx)x(0,Ly); the unknowns of one time-node are the
+ *    (nx-1)*(ny-1) interior points (Sec. 2).  Time-nodes 1..nt carry unknowns (node 0 is the
+ *    initial condition); dt = T/nt; the mass matrices are h*I with h = dt*(Lx/nx)*(Ly/ny).
+ *  - Layout of a KKT vector (3*nt*(ny-1)*(nx-1) doubles, contiguous): field-major u | z | w;
+ *    inside a field time-node-major (n = 1..nt), inside a slice row-major with x fastest:
+ *        offset(f, n, j, i) = ((f*nt + n-1)*(ny-1) + j-1)*(nx-1) + i-1.
+ *  - Every array argument is a DEVICE pointer to float64 data on the device the handle was
+ *    created on, owned by the caller, and must not alias another argument unless stated.
+ *  - Calls are ordered on the handle's HIP stream and return once the work is enqueued,
+ *    except fgmres_solve and kkt_solve_batched, which synchronise before returning.
+ *  - Return codes: KKTDD_OK (0), KKTDD_NOT_CONVERGED (1, x holds the last iterate), or a
+ *    negative error; no C++ exception crosses this boundary.  kkt_last_error() gives a
+ *    human-readable message for the last failing call of the calling thread.
+ *  - Sign reading: J_hat = J + (dt/sqrt(omega)) I, i.e. the diagonal shift of Eq. (7) that
+ *    enlarges J_hat's diagonal blocks (sigma = 1 + dt/sqrt(omega)).
+ */
+#ifndef KKTDD_H
+#define KKTDD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum kktdd_status {
+  KKTDD_OK = 0,
+  KKTDD_NOT_CONVERGED = 1, /* maxit reached; x holds the last iterate                        */
+  KKTDD_EINVAL = -1,       /* parameter outside the method's domain (see kkt_validate)        */
+  KKTDD_ENOMEM = -2,       /* the memory plan does not fit the device's free memory          */
+  KKTDD_EHIP = -3,         /* a HIP runtime call failed (message in kkt_last_error)           */
+  KKTDD_EBREAKDOWN = -4    /* non-finite residual or Hessenberg entry                         */
+};
+
+/* Arithmetic of the fine-level sweeps and their sine-transform GEMMs.  The KKT matvec, the
+ * Krylov vectors, the coarse level and every reduction stay float64. */
+enum kktdd_precision {
+  KKTDD_FP64 = 0,   /* float64 MFMA                                                        */
+  KKTDD_FP32 = 1    /* float32 MFMA, float32 sweep state; float64 outer refinement          */
+};
+
+/* Problem of Eq. (1) discretised as in Sec. 2, and the time decomposition of Sec. 3. */
+typedef struct kktdd_problem {
+  int32_t nx, ny;     /* grid intervals, >= 2                                              */
+  double Lx, Ly;      /* domain extents, > 0                                               */
+  int32_t nt;         /* time steps N_t, >= 1                                              */
+  double T;           /* final time, > 0                                                   */
+  double nu;          /* heat conductivity, > 0                                            */
+  double omega;       /* regularisation parameter, > 0                                    */
+  int32_t n_sub;      /* time subdomains N_D >= 1, must divide nt                         */
+  int32_t overlap;    /* delta: nodes each subdomain extends to the left, 0..nt/n_sub      */
+  int32_t coarse;     /* 0: one-level RASQ; 1: constant coarse basis; 2: constant+linear   */
+  int32_t precision;  /* enum kktdd_precision                                              */
+} kktdd_problem;
+
+typedef struct kktdd_stats {
+  int32_t iters;          /* Arnoldi steps over all cycles                                 */
+  int32_t restarts;       /* cycles after the first                                        */
+  int32_t status;         /* return code of the solve                                      */
+  int32_t reorth;         /* Arnoldi steps that needed a second Gram-Schmidt pass          */
+  double relres_est;      /* Givens estimate |g_{j+1}| / ||f|| at exit                     */
+  double relres_true;     /* ||f - K x|| / ||f|| at exit                                   */
+  double relres_block[3]; /* per-block ||f_b - (K x)_b|| / ||f_b|| (u, z, w; 0 if f_b = 0) */
+  double solve_s;         /* wall time of the solve                                        */
+} kktdd_stats;
+
+typedef struct kktdd_handle kktdd_handle;
+
+/* Host-only check of a problem description; touches no device.  Rules: nx, ny >= 2;
+ * nt >= 1; Lx, Ly, T, nu, omega positive and finite; n_sub >= 1 dividing nt;
+ * 0 <= overlap <= nt/n_sub; coarse in {0,1,2}; coarse == 2 needs nt/n_sub >= 2 (the linear
+ * basis function of Eq. (14) is constant on a one-step subdomain); precision known.
+ * Returns KKTDD_OK or KKTDD_EINVAL. */
+int kkt_validate(const kktdd_problem* prob);
+
+/* Device bytes kkt_create allocates for `prob`, plus what fgmres_solve adds for restart
+ * length `restart` (0: creation only).  Host-only.  Returns KKTDD_OK or KKTDD_EINVAL. */
+int kkt_memory_plan(const kktdd_problem* prob, int32_t restart, size_t* bytes);
+
+/* Create a handle on the current HIP device: validate, check the memory plan against the
+ * free device memory (KKTDD_ENOMEM before any allocation), build the sine and eigenvalue
+ * tables and factor the coarse operator of every sine mode (Sec. 3, S_hat_0 = R_0 S_hat R_0^T).
+ * `hip_stream` is a hipStream_t (NULL: the default stream).  On error *out is NULL. */
+int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out);
+
+/* Release every device buffer of the handle (NULL is ignored).  Synchronises its stream. */
+void kkt_destroy(kktdd_handle* h);
+
+/* Number of KKT unknowns, 3*nt*(nx-1)*(ny-1); 0 for NULL. */
+size_t kkt_size(const kktdd_handle* h);
+
+/* Right-hand side of Eq. (5): f_u = h*utilde(t_n), f_z = 0, f_w = (u0, 0, ..., 0)
+ * (Sec. 2: f carries the initial condition).
+ * u0: (ny-1)*(nx-1) doubles, x fastest; utilde: nt slices, slice n-1 sampled at t_n = n*dt;
+ * f: kkt_size doubles. */
+int kkt_rhs(kktdd_handle* h, const double* u0, const double* utilde, double* f);
+
+/* y = K x, the KKT matvec of Eq. (5) in float64.  x and y: kkt_size doubles; no aliasing. */
+int kkt_apply(kktdd_handle* h, const double* x, double* y);
+
+/* z = P^{-1} r for the block preconditioner of Eq. (7): z_u = r_u/h, z_z = r_z/(omega h),
+ * z_w = S_2level^{-1} r_w (Eqs. (13)-(15); coarse = 0 gives the one-level RASQ).
+ * r and z: kkt_size doubles; no aliasing. */
+int precond_apply(kktdd_handle* h, const double* r, double* z);
+
+/* x = D^{-1} b slice by slice, D = shift*I + dt*nu*A_h: the Dirichlet spatial solve done at
+ * every step of a time sweep (Sec. 4 "direct solve"), as sine-transform GEMMs in the
+ * handle's precision.  b, x: nslices*(ny-1)*(nx-1) doubles; may alias. */
+int kkt_spatial_solve(kktdd_handle* h, const double* b, double* x, int32_t nslices, double shift);
+
+/* Solve K x = f by flexible GMRES(restart) right-preconditioned with P (Sec. 4).  x holds the
+ * initial guess on entry and the iterate on exit.  Stops at the first Arnoldi step whose
+ * rotated residual estimate is <= rtol*||f||, confirmed by the true residual (a new cycle
+ * starts otherwise), or after maxit Arnoldi steps (KKTDD_NOT_CONVERGED).  f = 0 returns x = 0.
+ * Allocates the Krylov basis on first use of a restart length.  `stats` may be NULL. */
+int fgmres_solve(kktdd_handle* h, const double* f, double* x, int32_t restart, int32_t maxit,
+                 double rtol, kktdd_stats* stats);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* kkt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KKTDD_H */

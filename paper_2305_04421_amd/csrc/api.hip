@@ -1,0 +1,663 @@
+// Host driver of libkktdd: the C ABI declared in include/kktdd.h.
+//
+// Owns the handle (tables, work buffers, Krylov storage), validates problems, plans memory,
+// orchestrates the preconditioner (Eqs. (7), (13)-(15)) and runs flexible GMRES (Sec. 4).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace kktdd {
+
+namespace {
+thread_local std::string g_last_error;
+constexpr int kRedBlocks = 1024;   // blocks of the two-stage reductions
+constexpr double kReorthEta = 0.70710678118654752;  // 1/sqrt(2)
+}  // namespace
+
+int set_error(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+  return set_error(KKTDD_EHIP, buf);
+}
+
+}  // namespace kktdd
+
+using namespace kktdd;
+
+struct kktdd_handle {
+  kktdd_problem prob{};
+  Geom g{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int elem = 8;                       // bytes per element of the sweep work buffers
+  std::vector<void*> allocations;
+
+  // tables
+  double *Sx64 = nullptr, *Sy64 = nullptr, *invlam64 = nullptr;
+  float *Sx32 = nullptr, *Sy32 = nullptr, *invlam32 = nullptr;
+  double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
+  // sweeps
+  void *Tbuf = nullptr, *Ubuf = nullptr, *Ybuf = nullptr;
+  double* rprime = nullptr;
+  // coarse
+  double *r0 = nullptr, *c0 = nullptr, *Dc0 = nullptr, *DDc0 = nullptr;
+  double *chat = nullptr, *ctmp = nullptr, *cfac = nullptr;
+  // reductions
+  double *partials = nullptr, *sums = nullptr;
+  double* host_sums = nullptr;                 // pinned
+  // Krylov
+  int R = 0;
+  double *V = nullptr, *Zw = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
+  int* gate = nullptr;
+  double* host_hcol = nullptr;                 // pinned
+
+  const void* Sx() const { return prob.precision == KKTDD_FP32 ? (const void*)Sx32 : (const void*)Sx64; }
+  const void* Sy() const { return prob.precision == KKTDD_FP32 ? (const void*)Sy32 : (const void*)Sy64; }
+  const void* invlam() const {
+    return prob.precision == KKTDD_FP32 ? (const void*)invlam32 : (const void*)invlam64;
+  }
+};
+
+namespace {
+
+template <typename T>
+int dalloc(kktdd_handle* h, T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) return 0;
+  void* q = nullptr;
+  hipError_t e = hipMalloc(&q, count * sizeof(T));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed: %s", count * sizeof(T),
+                  hipGetErrorString(e));
+    return set_error(e == hipErrorOutOfMemory ? KKTDD_ENOMEM : KKTDD_EHIP, buf);
+  }
+  h->allocations.push_back(q);
+  *p = static_cast<T*>(q);
+  return 0;
+}
+
+int validate(const kktdd_problem* p) {
+  if (!p) return set_error(KKTDD_EINVAL, "problem is NULL");
+  auto bad = [](const char* m) { return set_error(KKTDD_EINVAL, m); };
+  if (p->nx < 2 || p->ny < 2) return bad("nx and ny must be >= 2");
+  if (p->nx > 1024 || p->ny > 1024) return bad("nx and ny must be <= 1024");
+  if (p->nt < 1) return bad("nt must be >= 1");
+  const double pos[] = {p->Lx, p->Ly, p->T, p->nu, p->omega};
+  for (double v : pos)
+    if (!(v > 0.0) || !std::isfinite(v)) return bad("Lx, Ly, T, nu, omega must be positive and finite");
+  if (p->n_sub < 1 || p->nt % p->n_sub != 0) return bad("n_sub must be >= 1 and divide nt");
+  const int k = p->nt / p->n_sub;
+  if (p->overlap < 0 || p->overlap > k) return bad("overlap must satisfy 0 <= overlap <= nt/n_sub");
+  if (p->coarse < 0 || p->coarse > 2) return bad("coarse must be 0, 1 or 2");
+  if (p->coarse == 2 && k < 2) return bad("a linear coarse basis needs nt/n_sub >= 2");
+  if (p->precision != KKTDD_FP64 && p->precision != KKTDD_FP32) return bad("unknown precision");
+  if ((long long)p->nt * (p->nx - 1) * (p->ny - 1) > (1LL << 40)) return bad("problem too large");
+  return KKTDD_OK;
+}
+
+Geom make_geom(const kktdd_problem& p) {
+  Geom g{};
+  g.mx = p.nx - 1;
+  g.my = p.ny - 1;
+  g.Mx = round_up16(g.mx);
+  g.My = round_up16(g.my);
+  g.nt = p.nt;
+  g.nxy = g.mx * g.my;
+  g.P = (long long)g.nt * g.nxy;
+  const double dx = p.Lx / p.nx, dy = p.Ly / p.ny, dt = p.T / p.nt;
+  g.cx = dt * p.nu / (dx * dx);
+  g.cy = dt * p.nu / (dy * dy);
+  g.h = dt * dx * dy;
+  g.omega = p.omega;
+  g.dt = dt;
+  g.sigma = 1.0 + dt / std::sqrt(p.omega);
+  g.nd = p.n_sub;
+  g.k = p.nt / p.n_sub;
+  g.delta = p.overlap;
+  g.L = g.k + g.delta;
+  g.nb = p.coarse;
+  g.nc = g.nb * g.nd;
+  return g;
+}
+
+struct Plan {
+  size_t tables, sweeps, coarse, krylov;
+  size_t total() const { return tables + sweeps + coarse + krylov; }
+};
+
+Plan plan(const Geom& g, int precision, int R) {
+  const size_t el = precision == KKTDD_FP32 ? 4 : 8;
+  const size_t MM = (size_t)g.padded();
+  Plan p{};
+  p.tables = ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My + MM) * 12 + (size_t)(g.mx + g.my) * 8;
+  p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el + (size_t)g.P * 8;
+  if (g.nb > 0) {
+    const int hb = 2 * g.nb - 1;
+    p.coarse = (size_t)g.nc * g.nxy * 8 * 4 + (size_t)g.nc * MM * 8 * 2 +
+               (size_t)g.nxy * g.nc * (hb + 1) * 8;
+  }
+  p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
+  if (R > 0) p.krylov = ((size_t)(R + 1) * 3 + (size_t)R) * (size_t)g.P * 8 + 4096;
+  return p;
+}
+
+// sin(pi * r / n) with r reduced modulo 2n first, so the argument stays in [0, 2 pi)
+double sinpi_frac(long long r, long long n) {
+  r %= 2 * n;
+  return std::sin(M_PI * (double)r / (double)n);
+}
+
+int build_tables(kktdd_handle* H) {
+  const Geom& g = H->g;
+  const kktdd_problem& p = H->prob;
+  auto sine = [](int n, int M) {
+    std::vector<double> S((size_t)M * M, 0.0);
+    for (int a = 0; a < n - 1; ++a)
+      for (int b = 0; b < n - 1; ++b) S[(size_t)a * M + b] = sinpi_frac((long long)(a + 1) * (b + 1), n);
+    return S;
+  };
+  const double dx = p.Lx / p.nx, dy = p.Ly / p.ny, dtnu = g.dt * p.nu;
+  std::vector<double> lx(g.mx), ly(g.my);
+  for (int a = 0; a < g.mx; ++a) {
+    const double s = std::sin(M_PI * (a + 1) / (2.0 * p.nx));
+    lx[a] = dtnu * 4.0 / (dx * dx) * s * s;
+  }
+  for (int a = 0; a < g.my; ++a) {
+    const double s = std::sin(M_PI * (a + 1) / (2.0 * p.ny));
+    ly[a] = dtnu * 4.0 / (dy * dy) * s * s;
+  }
+  const std::vector<double> Sx = sine(p.nx, g.Mx), Sy = sine(p.ny, g.My);
+  const double norm = 4.0 / ((double)p.nx * p.ny);
+  std::vector<double> inv((size_t)g.padded(), 0.0);
+  for (int q = 0; q < g.my; ++q)
+    for (int a = 0; a < g.mx; ++a) inv[(size_t)q * g.Mx + a] = norm / (g.sigma + ly[q] + lx[a]);
+  auto to32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+
+  if (int e = dalloc(H, &H->Sx64, Sx.size())) return e;
+  if (int e = dalloc(H, &H->Sy64, Sy.size())) return e;
+  if (int e = dalloc(H, &H->invlam64, inv.size())) return e;
+  if (int e = dalloc(H, &H->Sx32, Sx.size())) return e;
+  if (int e = dalloc(H, &H->Sy32, Sy.size())) return e;
+  if (int e = dalloc(H, &H->invlam32, inv.size())) return e;
+  if (int e = dalloc(H, &H->lamx, lx.size())) return e;
+  if (int e = dalloc(H, &H->lamy, ly.size())) return e;
+  KKT_HIP(hipMemcpy(H->Sx64, Sx.data(), Sx.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->Sy64, Sy.data(), Sy.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->invlam64, inv.data(), inv.size() * 8, hipMemcpyHostToDevice));
+  const auto Sx32 = to32(Sx), Sy32 = to32(Sy), inv32 = to32(inv);
+  KKT_HIP(hipMemcpy(H->Sx32, Sx32.data(), Sx32.size() * 4, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->Sy32, Sy32.data(), Sy32.size() * 4, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->invlam32, inv32.data(), inv32.size() * 4, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->lamx, lx.data(), lx.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(H->lamy, ly.data(), ly.size() * 8, hipMemcpyHostToDevice));
+  return 0;
+}
+
+// Gram matrices of the coarse time basis in band storage G[i*(hb+1) + b] = G(i, i-b).
+int build_coarse(kktdd_handle* H) {
+  const Geom& g = H->g;
+  if (g.nb == 0) return 0;
+  const int hb = 2 * g.nb - 1, w = hb + 1, nc = g.nc;
+  std::vector<double> G2((size_t)nc * w, 0.0), G0((size_t)nc * w, 0.0), G1((size_t)nc * w, 0.0);
+  // basis values at node n (1-based): slots nb*s + b, s = (n-1)/k
+  auto basis = [&](int n, double* v) {
+    const int s = (n - 1) / g.k;
+    v[0] = 1.0;
+    v[1] = -1.0 + 2.0 * (double)(n - s * g.k) / g.k;
+    return g.nb * s;
+  };
+  auto add = [&](std::vector<double>& G, int a, int b, double val) {
+    if (a < b) std::swap(a, b);
+    if (a - b <= hb) G[(size_t)a * w + (a - b)] += val;
+  };
+  for (int n = 1; n <= g.nt; ++n) {
+    double va[2], vb[2];
+    const int sa = basis(n, va);
+    for (int a = 0; a < g.nb; ++a)
+      for (int b = 0; b < g.nb; ++b) {
+        if (sa + a < sa + b) continue;  // lower triangle once
+        add(G2, sa + a, sa + b, va[a] * va[b]);
+        if (n >= 2) add(G0, sa + a, sa + b, va[a] * va[b]);
+      }
+    if (n < g.nt) {
+      const int sb = basis(n + 1, vb);
+      // (E + E^T) couples n and n+1 symmetrically: Z(n,a) Z(n+1,b) + Z(n+1,a) Z(n,b)
+      for (int a = 0; a < g.nb; ++a)
+        for (int b = 0; b < g.nb; ++b) {
+          const int ia = sa + a, ib = sb + b;
+          // contributes to G1(ia, ib) and G1(ib, ia); store the lower one once
+          if (ia == ib) add(G1, ia, ib, 2.0 * va[a] * vb[b]);
+          else add(G1, ia, ib, va[a] * vb[b]);
+        }
+    }
+  }
+  double *dG2, *dG0, *dG1;
+  int* dinfo;
+  if (int e = dalloc(H, &dG2, G2.size())) return e;
+  if (int e = dalloc(H, &dG0, G0.size())) return e;
+  if (int e = dalloc(H, &dG1, G1.size())) return e;
+  if (int e = dalloc(H, &dinfo, 1)) return e;
+  KKT_HIP(hipMemcpy(dG2, G2.data(), G2.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(dG0, G0.data(), G0.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemcpy(dG1, G1.data(), G1.size() * 8, hipMemcpyHostToDevice));
+  KKT_HIP(hipMemset(dinfo, 0, sizeof(int)));
+  if (int e = dalloc(H, &H->cfac, (size_t)g.nxy * nc * w)) return e;
+  if (int e = launch_coarse_factor(g, dG2, dG0, dG1, H->lamx, H->lamy, H->cfac, dinfo, H->stream)) return e;
+  int info = 0;
+  KKT_HIP(hipMemcpyAsync(&info, dinfo, sizeof(int), hipMemcpyDeviceToHost, H->stream));
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  if (info) return set_error(KKTDD_EINVAL, "coarse operator not positive definite");
+  return 0;
+}
+
+int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
+  const Geom& g = H->g;
+  hipStream_t s = H->stream;
+  const double* c0 = nullptr;
+  if (g.nb > 0) {
+    if (int e = launch_restrict(g, rw, dscale, H->r0, s)) return e;
+    if (int e = launch_coarse_dst(g, H->Sx64, H->Sy64, H->r0, H->chat, H->ctmp, s)) return e;
+    if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
+    const double norm = 4.0 / ((double)H->prob.nx * H->prob.ny);
+    if (int e = launch_coarse_idst(g, H->Sx64, H->Sy64, H->chat, H->c0, H->ctmp, norm, s)) return e;
+    if (int e = launch_apply_D(g, H->c0, H->Dc0, g.nc, g.sigma, s)) return e;
+    if (int e = launch_apply_D(g, H->Dc0, H->DDc0, g.nc, g.sigma, s)) return e;
+    c0 = H->c0;
+  }
+  if (int e = launch_residual_prime(g, rw, dscale, c0, H->Dc0, H->DDc0, H->rprime, s)) return e;
+  return launch_sweeps(g, H->prob.precision, H->Sx(), H->Sy(), H->invlam(), H->rprime, c0, zw,
+                       H->Tbuf, H->Ubuf, H->Ybuf, s);
+}
+
+// squared norms of the three fields of a KKT vector, to the host (synchronises)
+int field_sumsq(kktdd_handle* H, const double* r, double out[3]) {
+  if (int e = launch_sumsq_blocks(H->g, r, H->partials, kRedBlocks, H->stream)) return e;
+  if (int e = launch_reduce_partials(H->partials, kRedBlocks, 3, H->sums, H->stream)) return e;
+  KKT_HIP(hipMemcpyAsync(H->host_sums, H->sums, 3 * sizeof(double), hipMemcpyDeviceToHost, H->stream));
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  for (int i = 0; i < 3; ++i) out[i] = H->host_sums[i];
+  return 0;
+}
+
+int ensure_krylov(kktdd_handle* H, int R) {
+  if (H->R >= R) return 0;
+  const Geom& g = H->g;
+  // free the previous basis
+  auto release = [&](void* p) {
+    if (!p) return;
+    for (auto it = H->allocations.begin(); it != H->allocations.end(); ++it)
+      if (*it == p) {
+        (void)hipFree(p);
+        H->allocations.erase(it);
+        break;
+      }
+  };
+  release(H->V);
+  release(H->Zw);
+  H->V = H->Zw = nullptr;
+  H->R = 0;
+  size_t free_b = 0, total_b = 0;
+  KKT_HIP(hipMemGetInfo(&free_b, &total_b));
+  const size_t need = ((size_t)(R + 1) * 3 + (size_t)R) * (size_t)g.P * 8;
+  if (need > free_b) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "Krylov basis for restart %d needs %zu bytes, %zu free", R, need, free_b);
+    return set_error(KKTDD_ENOMEM, buf);
+  }
+  if (int e = dalloc(H, &H->V, (size_t)(R + 1) * 3 * g.P)) return e;
+  if (int e = dalloc(H, &H->Zw, (size_t)R * g.P)) return e;
+  H->R = R;
+  return 0;
+}
+
+}  // namespace
+
+// ==========================================================================================
+extern "C" {
+
+int kkt_validate(const kktdd_problem* prob) { return validate(prob); }
+
+int kkt_memory_plan(const kktdd_problem* prob, int32_t restart, size_t* bytes) {
+  if (int e = validate(prob)) return e;
+  if (!bytes || restart < 0) return set_error(KKTDD_EINVAL, "bad memory-plan arguments");
+  *bytes = plan(make_geom(*prob), prob->precision, restart).total();
+  return KKTDD_OK;
+}
+
+int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) {
+  if (!out) return set_error(KKTDD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (int e = validate(prob)) return e;
+  kktdd_handle* H = new (std::nothrow) kktdd_handle;
+  if (!H) return set_error(KKTDD_ENOMEM, "host allocation failed");
+  H->prob = *prob;
+  H->g = make_geom(*prob);
+  H->stream = static_cast<hipStream_t>(hip_stream);
+  H->elem = prob->precision == KKTDD_FP32 ? 4 : 8;
+  auto fail = [&](int code) {
+    kkt_destroy(H);
+    return code;
+  };
+  if (hipGetDevice(&H->device) != hipSuccess) {
+    (void)hipGetLastError();
+    delete H;
+    return set_error(KKTDD_EHIP, "no HIP device");
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    (void)hipGetLastError();
+    delete H;
+    return set_error(KKTDD_EHIP, "hipMemGetInfo failed");
+  }
+  const Geom& g = H->g;
+  const Plan pl = plan(g, prob->precision, 0);
+  if (pl.total() > free_b) {
+    delete H;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "problem needs %zu bytes, %zu free", pl.total(), free_b);
+    return set_error(KKTDD_ENOMEM, buf);
+  }
+  if (int e = build_tables(H)) return fail(e);
+  const size_t MM = (size_t)g.padded();
+  const size_t el = H->elem;
+  {
+    unsigned char *t, *u, *y;
+    if (int e = dalloc(H, &t, (size_t)g.nd * MM * el)) return fail(e);
+    if (int e = dalloc(H, &u, (size_t)g.nd * MM * el)) return fail(e);
+    if (int e = dalloc(H, &y, (size_t)g.nd * g.L * MM * el)) return fail(e);
+    H->Tbuf = t;
+    H->Ubuf = u;
+    H->Ybuf = y;
+  }
+  if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
+  if (g.nb > 0) {
+    if (int e = dalloc(H, &H->r0, (size_t)g.nc * g.nxy)) return fail(e);
+    if (int e = dalloc(H, &H->c0, (size_t)g.nc * g.nxy)) return fail(e);
+    if (int e = dalloc(H, &H->Dc0, (size_t)g.nc * g.nxy)) return fail(e);
+    if (int e = dalloc(H, &H->DDc0, (size_t)g.nc * g.nxy)) return fail(e);
+    if (int e = dalloc(H, &H->chat, (size_t)g.nc * MM)) return fail(e);
+    if (int e = dalloc(H, &H->ctmp, (size_t)g.nc * MM)) return fail(e);
+    // padded sine-mode slices must start (and stay) zero outside the mode grid
+    if (hipMemsetAsync(H->chat, 0, (size_t)g.nc * MM * 8, H->stream) != hipSuccess ||
+        hipMemsetAsync(H->ctmp, 0, (size_t)g.nc * MM * 8, H->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(set_error(KKTDD_EHIP, "hipMemsetAsync failed"));
+    }
+  }
+  if (int e = dalloc(H, &H->partials, (size_t)kRedBlocks * 40)) return fail(e);
+  if (int e = dalloc(H, &H->sums, 128)) return fail(e);
+  if (hipHostMalloc((void**)&H->host_sums, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    H->host_sums = nullptr;
+    return fail(set_error(KKTDD_EHIP, "hipHostMalloc failed"));
+  }
+  if (int e = build_coarse(H)) return fail(e);
+  if (hipStreamSynchronize(H->stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(set_error(KKTDD_EHIP, "setup failed"));
+  }
+  *out = H;
+  return KKTDD_OK;
+}
+
+void kkt_destroy(kktdd_handle* H) {
+  if (!H) return;
+  (void)hipStreamSynchronize(H->stream);
+  for (void* p : H->allocations) (void)hipFree(p);
+  if (H->host_sums) (void)hipHostFree(H->host_sums);
+  if (H->host_hcol) (void)hipHostFree(H->host_hcol);
+  delete H;
+}
+
+size_t kkt_size(const kktdd_handle* H) { return H ? (size_t)(3 * H->g.P) : 0; }
+
+int kkt_rhs(kktdd_handle* H, const double* u0, const double* utilde, double* f) {
+  if (!H || !u0 || !utilde || !f) return set_error(KKTDD_EINVAL, "NULL argument");
+  return launch_rhs(H->g, u0, utilde, f, H->stream);
+}
+
+int kkt_apply(kktdd_handle* H, const double* x, double* y) {
+  if (!H || !x || !y) return set_error(KKTDD_EINVAL, "NULL argument");
+  if (x == y) return set_error(KKTDD_EINVAL, "x and y must not alias");
+  const Geom& g = H->g;
+  return launch_kkt_apply(g, x, x + g.P, x + 2 * g.P, 1.0, 1.0, 1.0, nullptr, nullptr, y,
+                          y + g.P, y + 2 * g.P, H->stream);
+}
+
+int precond_apply(kktdd_handle* H, const double* r, double* z) {
+  if (!H || !r || !z) return set_error(KKTDD_EINVAL, "NULL argument");
+  if (r == z) return set_error(KKTDD_EINVAL, "r and z must not alias");
+  const Geom& g = H->g;
+  if (int e = launch_scale(g.P, r, 1.0 / g.h, nullptr, z, H->stream)) return e;
+  if (int e = launch_scale(g.P, r + g.P, 1.0 / (g.omega * g.h), nullptr, z + g.P, H->stream)) return e;
+  return schur_apply(H, r + 2 * g.P, nullptr, z + 2 * g.P);
+}
+
+int kkt_spatial_solve(kktdd_handle* H, const double* b, double* x, int32_t nslices, double shift) {
+  if (!H || !b || !x) return set_error(KKTDD_EINVAL, "NULL argument");
+  if (nslices < 0 || !(shift > 0.0) || !std::isfinite(shift)) return set_error(KKTDD_EINVAL, "bad nslices or shift");
+  if (nslices == 0) return KKTDD_OK;
+  const Geom& g = H->g;
+  const kktdd_problem& p = H->prob;
+  const size_t MM = (size_t)g.padded();
+  // eigenvalue table for this shift (this diagnostic entry point allocates and synchronises)
+  const double dx = p.Lx / p.nx, dy = p.Ly / p.ny, dtnu = g.dt * p.nu;
+  const double norm = 4.0 / ((double)p.nx * p.ny);
+  std::vector<double> inv(MM, 0.0);
+  for (int q = 0; q < g.my; ++q) {
+    const double sy = std::sin(M_PI * (q + 1) / (2.0 * p.ny));
+    for (int a = 0; a < g.mx; ++a) {
+      const double sx = std::sin(M_PI * (a + 1) / (2.0 * p.nx));
+      inv[(size_t)q * g.Mx + a] =
+          norm / (shift + dtnu * 4.0 / (dx * dx) * sx * sx + dtnu * 4.0 / (dy * dy) * sy * sy);
+    }
+  }
+  const size_t el = H->elem;
+  void *tab = nullptr, *w1 = nullptr, *w2 = nullptr;
+  int rc = 0;
+  if (hipMalloc(&tab, MM * el) != hipSuccess || hipMalloc(&w1, (size_t)nslices * MM * el) != hipSuccess ||
+      hipMalloc(&w2, (size_t)nslices * MM * el) != hipSuccess) {
+    (void)hipGetLastError();
+    rc = set_error(KKTDD_ENOMEM, "work allocation failed");
+  }
+  if (!rc) {
+    hipError_t e;
+    if (el == 4) {
+      std::vector<float> f(inv.begin(), inv.end());
+      e = hipMemcpyAsync(tab, f.data(), MM * 4, hipMemcpyHostToDevice, H->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
+    } else {
+      e = hipMemcpyAsync(tab, inv.data(), MM * 8, hipMemcpyHostToDevice, H->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(H->stream);
+    }
+    if (e != hipSuccess) rc = hip_fail(e, "table upload", __FILE__, __LINE__);
+  }
+  if (!rc) rc = launch_spatial_solve(g, p.precision, H->Sx(), H->Sy(), tab, b, x, nslices, w1, w2, H->stream);
+  if (hipStreamSynchronize(H->stream) != hipSuccess && !rc) rc = set_error(KKTDD_EHIP, "spatial solve failed");
+  if (tab) (void)hipFree(tab);
+  if (w1) (void)hipFree(w1);
+  if (w2) (void)hipFree(w2);
+  return rc;
+}
+
+int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, int32_t maxit,
+                 double rtol, kktdd_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!H || !f || !x) return set_error(KKTDD_EINVAL, "NULL argument");
+  if (f == x) return set_error(KKTDD_EINVAL, "f and x must not alias");
+  if (restart < 1 || restart > 31 || maxit < 0 || !(rtol > 0.0))
+    return set_error(KKTDD_EINVAL, "need 1 <= restart <= 31, maxit >= 0, rtol > 0");
+  kktdd_stats st{};
+  const Geom& g = H->g;
+  hipStream_t s = H->stream;
+  const long long n3 = 3 * g.P;
+  if (int e = ensure_krylov(H, restart)) return e;
+  if (!H->hcol) {
+    if (int e = dalloc(H, &H->hcol, 3 * 40)) return e;
+    if (int e = dalloc(H, &H->vinv, 40)) return e;
+    if (int e = dalloc(H, &H->ydev, 40)) return e;
+    if (int e = dalloc(H, &H->gate, 1)) return e;
+    if (hipHostMalloc((void**)&H->host_hcol, 3 * 40 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      H->host_hcol = nullptr;
+      return set_error(KKTDD_EHIP, "hipHostMalloc failed");
+    }
+  }
+  double fb[3];
+  if (int e = field_sumsq(H, f, fb)) return e;
+  const double fnorm = std::sqrt(fb[0] + fb[1] + fb[2]);
+  auto finish = [&](int status, double est, const double rb[3]) {
+    st.status = status;
+    st.relres_est = est;
+    const double rn = std::sqrt(rb[0] + rb[1] + rb[2]);
+    st.relres_true = fnorm > 0 ? rn / fnorm : 0.0;
+    for (int b = 0; b < 3; ++b) st.relres_block[b] = fb[b] > 0 ? std::sqrt(rb[b] / fb[b]) : 0.0;
+    st.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (stats) *stats = st;
+    return status;
+  };
+  if (!(std::isfinite(fnorm))) {
+    const double z[3] = {0, 0, 0};
+    finish(KKTDD_EBREAKDOWN, NAN, z);
+    return set_error(KKTDD_EBREAKDOWN, "non-finite right-hand side");
+  }
+  if (fnorm == 0.0) {
+    KKT_HIP(hipMemsetAsync(x, 0, (size_t)n3 * 8, s));
+    KKT_HIP(hipStreamSynchronize(s));
+    const double z[3] = {0, 0, 0};
+    return finish(KKTDD_OK, 0.0, z);
+  }
+  const double tol = rtol * fnorm;
+  const int R = restart;
+  const long long ldv = n3;
+  double* V = H->V;
+  double* Zw = H->Zw;
+  std::vector<double> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
+  double est = INFINITY;
+  int its = 0, cycles = 0;
+  while (true) {
+    // r = f - K x into V_0
+    if (int e = launch_kkt_apply(g, x, x + g.P, x + 2 * g.P, 1.0, 1.0, 1.0, nullptr, f, V,
+                                 V + g.P, V + 2 * g.P, s)) return e;
+    double rb[3];
+    if (int e = field_sumsq(H, V, rb)) return e;
+    const double beta = std::sqrt(rb[0] + rb[1] + rb[2]);
+    if (!std::isfinite(beta)) {
+      finish(KKTDD_EBREAKDOWN, est, rb);
+      return set_error(KKTDD_EBREAKDOWN, "non-finite residual");
+    }
+    if (beta <= tol) {
+      st.iters = its;
+      st.restarts = cycles > 0 ? cycles - 1 : 0;
+      return finish(KKTDD_OK, cycles ? est : beta / fnorm, rb);
+    }
+    if (its >= maxit) {
+      st.iters = its;
+      st.restarts = cycles > 0 ? cycles - 1 : 0;
+      return finish(KKTDD_NOT_CONVERGED, cycles ? est : beta / fnorm, rb);
+    }
+    ++cycles;
+    H->host_sums[4] = 1.0 / beta;   // pinned staging slot
+    KKT_HIP(hipMemcpyAsync(H->vinv, H->host_sums + 4, sizeof(double), hipMemcpyHostToDevice, s));
+    std::fill(Hm.begin(), Hm.end(), 0.0);
+    std::fill(gv.begin(), gv.end(), 0.0);
+    gv[0] = beta;
+    int jend = 0;
+    bool breakdown = false;
+    for (int j = 0; j < R; ++j) {
+      double* vj = V + (long long)j * ldv;
+      double* w = V + (long long)(j + 1) * ldv;
+      double* zwj = Zw + (long long)j * g.P;
+      // z_j = P^{-1} v_j: u and z blocks are v scaled (folded into the matvec), w block stored
+      if (int e = schur_apply(H, vj + 2 * g.P, H->vinv + j, zwj)) return e;
+      // w = K z_j
+      if (int e = launch_kkt_apply(g, vj, vj + g.P, zwj, 1.0 / g.h, 1.0 / (g.omega * g.h), 1.0,
+                                   H->vinv + j, nullptr, w, w + g.P, w + 2 * g.P, s)) return e;
+      const int nv = j + 1;
+      // separate slots so the three stages do not overwrite each other
+      double* sums1 = H->sums;
+      double* sums2 = H->sums + 40;
+      double* sums3 = H->sums + 80;
+      // pass A: <v_i, w>, ||w||
+      if (int e = launch_multidot(n3, V, ldv, nv, H->vinv, w, 1, H->partials, kRedBlocks, s)) return e;
+      if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums1, s)) return e;
+      if (int e = launch_arnoldi_finish(j, sums1, nullptr, nullptr, H->gate, H->hcol, H->vinv,
+                                        kReorthEta, 1, s)) return e;
+      // pass B: w -= V h; <v_i, w1>, ||w1||
+      if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 1,
+                                    H->partials, kRedBlocks, nullptr, s)) return e;
+      if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums2, s)) return e;
+      if (int e = launch_arnoldi_finish(j, nullptr, sums2, nullptr, H->gate, H->hcol, H->vinv,
+                                        kReorthEta, 2, s)) return e;
+      // pass C (only if the gate is set): w -= V h2; ||w2||
+      if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 0,
+                                    H->partials, kRedBlocks, H->gate, s)) return e;
+      if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums3, s)) return e;
+      if (int e = launch_arnoldi_finish(j, nullptr, nullptr, sums3, H->gate, H->hcol,
+                                        H->vinv, kReorthEta, 3, s)) return e;
+      KKT_HIP(hipMemcpyAsync(H->host_hcol, H->hcol, (j + 3) * sizeof(double),
+                             hipMemcpyDeviceToHost, s));
+      KKT_HIP(hipStreamSynchronize(s));
+      const double* hc = H->host_hcol;
+      if (hc[j + 2] != 0.0) ++st.reorth;
+      for (int i = 0; i <= j + 1; ++i) {
+        if (!std::isfinite(hc[i])) {
+          const double z3[3] = {NAN, NAN, NAN};
+          st.iters = its;
+          finish(KKTDD_EBREAKDOWN, est, z3);
+          return set_error(KKTDD_EBREAKDOWN, "non-finite Hessenberg entry");
+        }
+        Hm[(size_t)i * R + j] = hc[i];
+      }
+      // apply previous rotations, then the new one
+      for (int i = 0; i < j; ++i) {
+        const double a = Hm[(size_t)i * R + j], b = Hm[(size_t)(i + 1) * R + j];
+        Hm[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
+        Hm[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = Hm[(size_t)j * R + j], b = Hm[(size_t)(j + 1) * R + j];
+      const double rho = std::hypot(a, b);
+      cs[j] = rho == 0.0 ? 1.0 : a / rho;
+      sn[j] = rho == 0.0 ? 0.0 : b / rho;
+      Hm[(size_t)j * R + j] = rho;
+      Hm[(size_t)(j + 1) * R + j] = 0.0;
+      gv[j + 1] = -sn[j] * gv[j];
+      gv[j] = cs[j] * gv[j];
+      ++its;
+      est = std::fabs(gv[j + 1]) / fnorm;
+      jend = j + 1;
+      breakdown = (b == 0.0);
+      if (std::fabs(gv[j + 1]) <= tol || its >= maxit || breakdown) break;
+    }
+    // x += Z y with y from the rotated triangular system
+    for (int i = jend - 1; i >= 0; --i) {
+      double t = gv[i];
+      for (int m = i + 1; m < jend; ++m) t -= Hm[(size_t)i * R + m] * y[m];
+      y[i] = t / Hm[(size_t)i * R + i];
+    }
+    std::copy(y.begin(), y.begin() + jend, H->host_sums + 32);   // pinned staging slots
+    KKT_HIP(hipMemcpyAsync(H->ydev, H->host_sums + 32, jend * sizeof(double), hipMemcpyHostToDevice, s));
+    if (int e = launch_update_solution(g, V, ldv, Zw, g.P, jend, H->ydev, H->vinv, 1.0 / g.h,
+                                       1.0 / (g.omega * g.h), x, s)) return e;
+    (void)breakdown;
+  }
+}
+
+const char* kkt_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Nicolaides coarse time level (Sec. 3, Eq. (14)) and the multiplicative two-level residual.
+//
+// Coarse basis Z = Z_t (x) I: subdomain s (0-based, owned nodes s*k+1..(s+1)*k) has a
+// constant function and, with two functions per subdomain, the linear one
+// phi_1(n) = -1 + 2 (n - s*k)/k, both zero off its owned nodes.  Slot nb*s + b of a coarse
+// vector holds one full slice (every interior point) for basis function b of subdomain s.
+//
+// In sine-mode space S_hat = J_hat M^{-1} J_hat^T is block diagonal: mode (q,p) sees
+// (1/h) T(d) with d = sigma + dt*nu*(lam^y_q + lam^x_p) and T(d) = J_d J_d^T, J_d lower
+// bidiagonal (d on the diagonal, -1 below).  Hence S_hat_0 = Z^T S_hat Z is, mode by mode,
+// the small SPD band matrix (1/h)(d^2 G2 + G0 - d G1) with fixed Gram matrices
+// G2 = Z_t^T Z_t, G0 = Z_t^T diag(0,1,..,1) Z_t, G1 = Z_t^T (E + E^T) Z_t (E: time shift),
+// of half-bandwidth 2*nb - 1.  One thread factors / solves one mode.
+#include "internal.h"
+
+namespace kktdd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline double phi1(int node, int s, int k) {
+  return -1.0 + 2.0 * (double)(node - s * k) / (double)k;
+}
+
+// r0[nb*s + b][pt] = sum over owned nodes n of s of phi_b(n) * scale * r_w[n][pt]
+__global__ void __launch_bounds__(kBlock)
+k_restrict(Geom g, const double* __restrict__ rw, const double* __restrict__ dscale,
+           double* __restrict__ r0) {
+  const int pt = blockIdx.x * kBlock + threadIdx.x;
+  const int s = blockIdx.y;
+  if (pt >= g.nxy) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) {
+    const double v = rw[(long long)(n - 1) * g.nxy + pt];
+    a0 += v;
+    a1 += phi1(n, s, g.k) * v;
+  }
+  const double sc = dscale ? *dscale : 1.0;
+  r0[(long long)(g.nb * s) * g.nxy + pt] = sc * a0;
+  if (g.nb == 2) r0[(long long)(g.nb * s + 1) * g.nxy + pt] = sc * a1;
+}
+
+// Band storage of the Gram matrices: G[i*(hb+1) + b] = G(i, i-b), b = 0..hb.
+// Factor: fac[(i*(hb+1) + b) * nmodes + mode] = L(i, i-b) (lower Cholesky factor).
+__global__ void __launch_bounds__(kBlock)
+k_coarse_factor(Geom g, const double* __restrict__ G2, const double* __restrict__ G0,
+                const double* __restrict__ G1, const double* __restrict__ lamx,
+                const double* __restrict__ lamy, double* __restrict__ fac, int* info) {
+  const int mode = blockIdx.x * kBlock + threadIdx.x;
+  const int nmodes = g.nxy;
+  if (mode >= nmodes) return;
+  const int q = mode / g.mx, p = mode % g.mx;
+  const double d = g.sigma + lamy[q] + lamx[p];   // tables hold dt*nu*lambda
+  const int hb = 2 * g.nb - 1, w = hb + 1;
+  const double invh = 1.0 / g.h;
+  auto L = [&](int i, int j) -> double& { return fac[((long long)i * w + (i - j)) * nmodes + mode]; };
+  for (int i = 0; i < g.nc; ++i) {
+    const int j0 = i - hb > 0 ? i - hb : 0;
+    for (int j = j0; j <= i; ++j) {
+      const int b = i - j;
+      double a = (d * d * G2[i * w + b] + G0[i * w + b] - d * G1[i * w + b]) * invh;
+      for (int m = (i - hb > 0 ? i - hb : 0); m < j; ++m) {
+        if (j - m > hb) continue;
+        a -= L(i, m) * L(j, m);
+      }
+      if (j < i) {
+        L(i, j) = a / L(j, j);
+      } else {
+        if (!(a > 0.0)) {
+          *info = 1;
+          a = 1.0;
+        }
+        L(i, i) = sqrt(a);
+      }
+    }
+  }
+}
+
+// In-place solve of every mode's band system on padded sine-mode slices xhat[slot][q][p].
+__global__ void __launch_bounds__(kBlock)
+k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat) {
+  const int mode = blockIdx.x * kBlock + threadIdx.x;
+  const int nmodes = g.nxy;
+  if (mode >= nmodes) return;
+  const int q = mode / g.mx, p = mode % g.mx;
+  const long long MM = g.padded();
+  double* x = xhat + (long long)q * g.Mx + p;
+  const int hb = 2 * g.nb - 1, w = hb + 1;
+  auto L = [&](int i, int j) { return fac[((long long)i * w + (i - j)) * nmodes + mode]; };
+  // forward: L y = r
+  for (int i = 0; i < g.nc; ++i) {
+    double a = x[i * MM];
+    for (int j = (i - hb > 0 ? i - hb : 0); j < i; ++j) a -= L(i, j) * x[j * MM];
+    x[i * MM] = a / L(i, i);
+  }
+  // backward: L^T c = y
+  for (int i = g.nc - 1; i >= 0; --i) {
+    double a = x[i * MM];
+    for (int j = i + 1; j <= i + hb && j < g.nc; ++j) a -= L(j, i) * x[j * MM];
+    x[i * MM] = a / L(i, i);
+  }
+}
+
+// r'^n = scale*r_w^n - (S_hat c)^n, c^n = sum_b phi_b(n) c0[slot(n,b)] (prolongation Z c0).
+// With g^n = (J_hat^T c)^n = D c^n - c^{n+1} and (J_hat g)^n = D g^n - g^{n-1}:
+//     (S_hat c)^n = (1/h) (D^2 c^n - D c^{n+1} - [n>=2] (D c^{n-1} - c^n)),
+// where D c and D^2 c are prolonged from the precomputed D c0 and D^2 c0 (Z commutes with D).
+__device__ inline double prolong(const Geom& g, const double* __restrict__ slots, int node,
+                                 int pt) {
+  if (node < 1 || node > g.nt) return 0.0;
+  const int s = (node - 1) / g.k;
+  const double* c = slots + (long long)(g.nb * s) * g.nxy + pt;
+  double v = c[0];
+  if (g.nb == 2) v += phi1(node, s, g.k) * c[g.nxy];
+  return v;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict__ dscale,
+                 const double* __restrict__ c0, const double* __restrict__ Dc0,
+                 const double* __restrict__ DDc0, double* __restrict__ rp) {
+  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (e >= g.P) return;
+  const double sc = dscale ? *dscale : 1.0;
+  double v = sc * rw[e];
+  if (c0) {
+    const int n = (int)(e / g.nxy) + 1;
+    const int pt = (int)(e % g.nxy);
+    double Sc = prolong(g, DDc0, n, pt) - prolong(g, Dc0, n + 1, pt);
+    if (n >= 2) Sc -= prolong(g, Dc0, n - 1, pt) - prolong(g, c0, n, pt);
+    v -= Sc / g.h;
+  }
+  rp[e] = v;
+}
+
+}  // namespace
+
+int launch_restrict(const Geom& g, const double* rw, const double* dscale, double* r0,
+                    hipStream_t s) {
+  const dim3 grid((g.nxy + kBlock - 1) / kBlock, g.nd);
+  hipLaunchKernelGGL(k_restrict, grid, dim3(kBlock), 0, s, g, rw, dscale, r0);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_coarse_factor(const Geom& g, const double* G2, const double* G0, const double* G1,
+                         const double* lamx, const double* lamy, double* fac, int* info,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_factor, dim3((g.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
+                     G2, G0, G1, lamx, lamy, fac, info);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_solve, dim3((g.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
+                     fac, xhat);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
+                          const double* c0, const double* Dc0, const double* DDc0,
+                          double* rprime, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_prime, dim3((unsigned)((g.P + kBlock - 1) / kBlock)),
+                     dim3(kBlock), 0, s, g, rw, dscale, c0, Dc0, DDc0, rprime);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace kktdd

@@ -1,0 +1,116 @@
+// Internal declarations shared by the kernel files and the host driver of libkktdd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "kktdd.h"
+
+namespace kktdd {
+
+// ---------------------------------------------------------------------------------------
+// Geometry of one problem, passed by value to kernels.
+// A slice is (ny-1) x (nx-1) interior points, x fastest.  Sine-transform work buffers pad
+// both extents up to multiples of 16 (Mx, My) so every MFMA tile is full; padded rows and
+// columns of the sine matrices and eigenvalue tables are zero, so padding stays zero.
+// ---------------------------------------------------------------------------------------
+struct Geom {
+  int mx, my;          // interior points per row / per column
+  int Mx, My;          // padded extents (multiples of 16)
+  int nt;              // time-nodes carrying unknowns
+  int nxy;             // mx*my
+  long long P;         // nt*nxy: points of one field
+  double cx, cy;       // dt*nu/dx^2, dt*nu/dy^2
+  double h;            // dt*dx*dy (mass scale)
+  double omega, dt;
+  double sigma;        // 1 + dt/sqrt(omega): J_hat's diagonal shift
+  int nd, k, delta;    // time subdomains, steps per subdomain, overlap
+  int L;               // sweep length k + delta (subdomain 1 padded with zero nodes)
+  int nb;              // coarse basis functions per subdomain (0, 1, 2)
+  int nc;              // nb*nd coarse slots per point
+  __host__ __device__ long long padded() const { return (long long)Mx * My; }
+};
+
+inline int round_up16(int v) { return (v + 15) / 16 * 16; }
+
+// Launch helpers report through this; the host driver converts to KKTDD_EHIP.
+#define KKT_HIP(call)                                       \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::kktdd::hip_fail(e_, #call, __FILE__, __LINE__); \
+  } while (0)
+
+int hip_fail(hipError_t e, const char* what, const char* file, int line);
+int set_error(int code, const std::string& msg);
+
+// ---- stencil.hip: KKT matvec, right-hand side, block scalings, D_sigma stencil ----------
+// y = K [su*xu; sz*xz; sw*xw] (Eq. (5)); su and sz are further multiplied by the optional
+// device scalar *dscale (nullptr: 1).  If f != nullptr, y = f - K x instead.
+int launch_kkt_apply(const Geom& g, const double* xu, const double* xz, const double* xw,
+                     double su, double sz, double sw, const double* dscale,
+                     const double* f, double* yu, double* yz, double* yw, hipStream_t s);
+int launch_rhs(const Geom& g, const double* u0, const double* ut, double* f, hipStream_t s);
+// out = a*in (+ optional device scalar factor), n doubles
+int launch_scale(long long n, const double* in, double a, const double* dscale, double* out,
+                 hipStream_t s);
+// out = (shift I + dt nu A_h) in on nslices unpadded slices
+int launch_apply_D(const Geom& g, const double* in, double* out, int nslices, double shift,
+                   hipStream_t s);
+
+// ---- dst.hip: sine-transform GEMMs and the fine-level sweeps ---------------------------
+int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const void* Sy,
+                         const void* invlam, const double* b, double* x, int nslices,
+                         void* work1, void* work2, hipStream_t s);
+// Fine-level RASQ sweeps of Eq. (13) for every subdomain: reads r' (nt slices, float64),
+// writes z_w (nt slices) = c + x at owned nodes, c from the coarse slots c0 (nullptr: 0).
+int launch_sweeps(const Geom& g, int precision, const void* Sx, const void* Sy,
+                  const void* invlam, const double* rprime, const double* c0, double* zw,
+                  void* Tbuf, void* Ubuf, void* Ybuf, hipStream_t s);
+// Coarse sine transforms (float64): forward r0 (nc unpadded slices) -> rhat (padded), and
+// inverse chat (padded) -> c0 (unpadded, with the 4/(nx ny) normalisation).
+int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const double* r0,
+                      double* rhat, double* tmp, hipStream_t s);
+int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
+                       double* c0, double* tmp, double norm, hipStream_t s);
+
+// ---- coarse.hip: Nicolaides coarse level --------------------------------------------------
+int launch_restrict(const Geom& g, const double* rw, const double* dscale, double* r0,
+                    hipStream_t s);
+// Factor the banded SPD coarse operator of every sine mode; band (nc x (bw+1)) Gram pieces.
+int launch_coarse_factor(const Geom& g, const double* G2, const double* G0, const double* G1,
+                         const double* lamx, const double* lamy, double* fac, int* info,
+                         hipStream_t s);
+int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStream_t s);
+// r' = scale*r_w - S_hat c with c prolonged from c0; c0/Dc0/DDc0 may be nullptr (no coarse).
+int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
+                          const double* c0, const double* Dc0, const double* DDc0,
+                          double* rprime, hipStream_t s);
+
+// ---- krylov.hip: Arnoldi and vector kernels ------------------------------------------------
+// Per-block partial sums of the raw products <V_i, w> for i < nv and, if want_norm, <w, w>
+// at slot nv (the scales vinv are applied after the reduction).
+int launch_multidot(long long n, const double* V, long long ldv, int nv, const double* vinv,
+                    const double* w, int want_norm, double* partials, int nblocks,
+                    hipStream_t s);
+// w_out = w - sum_i coef[i] * vinv[i] * v_i, and partial sums of <v_i vinv[i], w_out> and
+// <w_out, w_out>.  If gate != nullptr and *gate == 0 the kernel does nothing.
+int launch_update_dot(long long n, const double* V, long long ldv, int nv, const double* vinv,
+                      const double* coef, const double* w, double* wout, int want_dots,
+                      double* partials, int nblocks, const int* gate, hipStream_t s);
+int launch_reduce_partials(const double* partials, int nblocks, int nsums, double* out,
+                           hipStream_t s);
+// Arnoldi bookkeeping on the device (one thread): see krylov.hip.
+int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const double* sums3,
+                          int* gate, double* hcol, double* vinv, double eta, int stage,
+                          hipStream_t s);
+// x_f += sum_i y[i] * fscale_f * vinv[i] * V_i,f for f = u, z; x_w += sum_i y[i] * Zw_i.
+int launch_update_solution(const Geom& g, const double* V, long long ldv, const double* Zw,
+                           long long ldz, int nv, const double* y, const double* vinv,
+                           double su, double sz, double* x, hipStream_t s);
+int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
+                        hipStream_t s);
+
+}  // namespace kktdd

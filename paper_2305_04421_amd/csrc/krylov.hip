@@ -1,0 +1,284 @@
+// Flexible GMRES vector kernels (float64): Arnoldi Gram-Schmidt passes, reductions,
+// solution update.
+//
+// Krylov vectors are stored unnormalised: the basis vector is v_i = vinv[i] * V_i with the
+// scale vinv[i] kept on the device, so normalising a new vector costs no extra pass.
+// Arnoldi step j orthogonalises w = K z_j against v_0..v_j by classical Gram-Schmidt with
+// selective reorthogonalisation (Daniel-Gragg-Kaufman-Stewart): pass A forms <v_i, w> and
+// ||w||; pass B subtracts the projections and, reading the same V, also forms
+// <v_i, w1> and ||w1||; only if ||w1|| < eta ||w|| does pass C subtract the second
+// projections.  Every reduction is two-stage and in a fixed order, so results are
+// deterministic.
+#include "internal.h"
+
+namespace kktdd {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum `count` per-thread values over the block; thread 0 writes out[0..count).
+template <int MAXS>
+__device__ inline void block_sums(double (&acc)[MAXS], int count, double* out) {
+  __shared__ double red[kBlock / 64][MAXS];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i) {
+    if (i < count) {
+      const double v = wave_sum(acc[i]);
+      if (lane == 0) red[wave][i] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < count) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) t += red[w][threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(kBlock)
+k_multidot(long long n, const double* __restrict__ V, long long ldv, int nv,
+           const double* __restrict__ w, int want_norm, double* __restrict__ partials) {
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i) acc[i] = 0.0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
+    const double wv = w[e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < nv) acc[i] += V[i * ldv + e] * wv;
+    acc[MAXV] += wv * wv;
+  }
+  // compact: slot nv holds the norm
+  double out[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i) out[i] = i < nv ? acc[i] : 0.0;
+  if (want_norm) {
+#pragma unroll
+    for (int i = 0; i <= MAXV; ++i)
+      if (i == nv) out[i] = acc[MAXV];
+  }
+  block_sums<MAXV + 1>(out, nv + (want_norm ? 1 : 0), partials + (long long)blockIdx.x * (nv + (want_norm ? 1 : 0)));
+}
+
+template <int MAXV>
+__global__ void __launch_bounds__(kBlock)
+k_update_dot(long long n, const double* __restrict__ V, long long ldv, int nv,
+             const double* __restrict__ vinv, const double* __restrict__ coef,
+             const double* w, double* wout, int want_dots, double* __restrict__ partials,
+             const int* __restrict__ gate) {
+  if (gate && *gate == 0) return;
+  double cf[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) cf[i] = i < nv ? coef[i] * vinv[i] : 0.0;
+  double acc[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i) acc[i] = 0.0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
+    double vv[MAXV];
+    double x = w[e];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      vv[i] = i < nv ? V[i * ldv + e] : 0.0;
+      x -= cf[i] * vv[i];
+    }
+    wout[e] = x;
+    if (want_dots) {
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i) acc[i] += vv[i] * x;
+    }
+    acc[MAXV] += x * x;
+  }
+  const int ns = (want_dots ? nv : 0) + 1;
+  double out[MAXV + 1];
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i) out[i] = (want_dots && i < nv) ? acc[i] : 0.0;
+#pragma unroll
+  for (int i = 0; i <= MAXV; ++i)
+    if (i == ns - 1) out[i] = acc[MAXV];
+  block_sums<MAXV + 1>(out, ns, partials + (long long)blockIdx.x * ns);
+}
+
+// out[i] = sum over blocks of partials[b*nsums + i], in block order.
+__global__ void __launch_bounds__(kBlock)
+k_reduce_partials(const double* __restrict__ partials, int nblocks, int nsums,
+                  double* __restrict__ out) {
+  __shared__ double red[kBlock];
+  for (int i = 0; i < nsums; ++i) {
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[(long long)b * nsums + i];
+    red[threadIdx.x] = t;
+    __syncthreads();
+    for (int h = kBlock / 2; h > 0; h >>= 1) {
+      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[i] = red[0];
+    __syncthreads();
+  }
+}
+
+// Arnoldi bookkeeping for step j (one thread).
+//   hcol[0..j]   : Hessenberg column (projections, accumulated over both passes)
+//   hcol[j+1]    : ||w|| after orthogonalisation = H(j+1, j)
+//   hcol[j+2]    : 1 if a second pass was taken
+//   coef[0..j]   : coefficients of the next update pass (stored right after hcol)
+// stage 1: sums1 = raw <V_i, w>, ||w||^2      -> coef = h, hcol = h, keep ||w||
+// stage 2: sums2 = raw <V_i, w1>, ||w1||^2    -> reorthogonalise if ||w1|| < eta ||w||
+// stage 3: sums3 = ||w2||^2 (only if gated)
+__global__ void k_arnoldi_finish(int j, const double* sums1, const double* sums2,
+                                 const double* sums3, int* gate, double* hcol, double* vinv,
+                                 double eta, int stage) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* coef = hcol + (j + 3);
+  double* wnorm = hcol + 2 * (j + 3);   // scratch: ||w|| of pass A
+  if (stage == 1) {
+    for (int i = 0; i <= j; ++i) {
+      const double h = vinv[i] * sums1[i];
+      hcol[i] = h;
+      coef[i] = h;
+    }
+    wnorm[0] = sqrt(sums1[j + 1]);
+    hcol[j + 2] = 0.0;
+    *gate = 0;
+  } else if (stage == 2) {
+    const double n1 = sqrt(sums2[j + 1]);
+    if (n1 < eta * wnorm[0]) {
+      for (int i = 0; i <= j; ++i) {
+        const double h = vinv[i] * sums2[i];
+        hcol[i] += h;
+        coef[i] = h;
+      }
+      hcol[j + 2] = 1.0;
+      *gate = 1;
+    } else {
+      hcol[j + 1] = n1;
+      vinv[j + 1] = n1 > 0.0 ? 1.0 / n1 : 0.0;
+      *gate = 0;
+    }
+  } else if (*gate) {
+    const double n2 = sqrt(sums3[0]);
+    hcol[j + 1] = n2;
+    vinv[j + 1] = n2 > 0.0 ? 1.0 / n2 : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_update_solution(Geom g, const double* __restrict__ V, long long ldv,
+                  const double* __restrict__ Zw, long long ldz, int nv,
+                  const double* __restrict__ y, const double* __restrict__ vinv, double su,
+                  double sz, double* __restrict__ x) {
+  const long long n3 = 3 * g.P;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n3; e += stride) {
+    const int f = (int)(e / g.P);
+    double acc = 0.0;
+    if (f < 2) {
+      const double sf = f == 0 ? su : sz;
+      for (int i = 0; i < nv; ++i) acc += (y[i] * vinv[i] * sf) * V[i * ldv + e];
+    } else {
+      const long long off = e - 2 * g.P;
+      for (int i = 0; i < nv; ++i) acc += y[i] * Zw[i * ldz + off];
+    }
+    x[e] += acc;
+  }
+}
+
+// partials[b*3 + f] = sum of squares of field f over this block's share.
+__global__ void __launch_bounds__(kBlock)
+k_sumsq_blocks(Geom g, const double* __restrict__ r, double* __restrict__ partials) {
+  double acc[3] = {0.0, 0.0, 0.0};
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < g.P; e += stride) {
+    const double a = r[e], b = r[g.P + e], c = r[2 * g.P + e];
+    acc[0] += a * a;
+    acc[1] += b * b;
+    acc[2] += c * c;
+  }
+  block_sums<3>(acc, 3, partials + (long long)blockIdx.x * 3);
+}
+
+}  // namespace
+
+int launch_multidot(long long n, const double* V, long long ldv, int nv, const double* vinv,
+                    const double* w, int want_norm, double* partials, int nblocks,
+                    hipStream_t s) {
+  (void)vinv;
+  const dim3 grid(nblocks), block(kBlock);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_multidot<8>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_multidot<16>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
+  else if (nv <= 32)
+    hipLaunchKernelGGL((k_multidot<32>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
+  else
+    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_update_dot(long long n, const double* V, long long ldv, int nv, const double* vinv,
+                      const double* coef, const double* w, double* wout, int want_dots,
+                      double* partials, int nblocks, const int* gate, hipStream_t s) {
+  const dim3 grid(nblocks), block(kBlock);
+  if (nv <= 8)
+    hipLaunchKernelGGL((k_update_dot<8>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
+                       want_dots, partials, gate);
+  else if (nv <= 16)
+    hipLaunchKernelGGL((k_update_dot<16>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
+                       want_dots, partials, gate);
+  else if (nv <= 32)
+    hipLaunchKernelGGL((k_update_dot<32>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
+                       want_dots, partials, gate);
+  else
+    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_reduce_partials(const double* partials, int nblocks, int nsums, double* out,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, partials, nblocks, nsums, out);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const double* sums3,
+                          int* gate, double* hcol, double* vinv, double eta, int stage,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, j, sums1, sums2, sums3, gate, hcol,
+                     vinv, eta, stage);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_update_solution(const Geom& g, const double* V, long long ldv, const double* Zw,
+                           long long ldz, int nv, const double* y, const double* vinv,
+                           double su, double sz, double* x, hipStream_t s) {
+  const long long n3 = 3 * g.P;
+  long long nb = (n3 + kBlock - 1) / kBlock;
+  if (nb > 8192) nb = 8192;
+  hipLaunchKernelGGL(k_update_solution, dim3((unsigned)nb), dim3(kBlock), 0, s, g, V, ldv, Zw, ldz,
+                     nv, y, vinv, su, sz, x);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_sumsq_blocks, dim3(nblocks), dim3(kBlock), 0, s, g, r, partials);
+  KKT_HIP(hipGetLastError());
+  return 0;
+}
+
+}  // namespace kktdd

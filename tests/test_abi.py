@@ -1,0 +1,88 @@
+"""The C-ABI library: it loads, exports every entry point its header declares, and rejects
+bad problems in host-only validation.  No device call is made here."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kktdd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2305_04421_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2305_04421_amd import build
+        build.build()
+    return _lib.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kkt_\w+|precond_apply|fgmres_solve)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for want in ("kkt_create", "kkt_destroy", "kkt_size", "kkt_rhs", "kkt_apply", "precond_apply",
+                 "fgmres_solve", "kkt_last_error", "kkt_validate", "kkt_memory_plan", "kkt_spatial_solve"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    from paper_2305_04421_amd import _lib
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    assert set(_declared_functions()) == set(_lib.EXPORTED)
+
+
+def _prob(**kw):
+    from paper_2305_04421_amd import _lib
+    base = dict(nx=32, ny=32, nt=32, Lx=1.0, Ly=1.0, T=1.0, nu=1.0, omega=1e-2, n_sub=4, overlap=2, coarse=2)
+    base.update(kw)
+    prec = base.pop("precision", "fp64")
+    return _lib.make_problem(base, prec)
+
+
+def test_validate_accepts_the_configurations(lib):
+    from paper_2305_04421_amd import workloads as wl
+    for name in ("tiny32", "grid128", "grid128_w4", "grid256", "grid512"):
+        params, _ = wl.config(name)
+        for prec in ("fp64", "fp32"):
+            p = _prob(**dict(params, precision=prec))
+            assert lib.kkt_validate(ctypes.byref(p)) == 0, name
+
+
+@pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(nx=1025), dict(nt=0), dict(omega=0.0),
+                                 dict(nu=-1.0), dict(T=float("inf")), dict(Lx=0.0), dict(n_sub=5),
+                                 dict(overlap=9), dict(overlap=-1), dict(coarse=3), dict(n_sub=32, coarse=2),
+                                 dict(precision=7)])
+def test_validate_rejects_bad_problems(lib, bad):
+    from paper_2305_04421_amd import _lib
+    p = _prob(**bad)
+    assert lib.kkt_validate(ctypes.byref(p)) == _lib.EINVAL
+    assert len(lib.kkt_last_error()) > 0
+
+
+def test_memory_plan_grows_with_restart(lib):
+    p = _prob(nx=128, ny=128, nt=256, n_sub=16)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.kkt_memory_plan(ctypes.byref(p), 0, ctypes.byref(a)) == 0
+    assert lib.kkt_memory_plan(ctypes.byref(p), 30, ctypes.byref(b)) == 0
+    P = 127 * 127 * 256
+    # the basis holds 31 three-field vectors and 30 w-blocks in float64
+    assert b.value - a.value >= (31 * 3 + 30) * P * 8
+    assert lib.kkt_memory_plan(ctypes.byref(p), -1, ctypes.byref(b)) < 0
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    from paper_2305_04421_amd import _lib
+    assert lib.kkt_create(None, None, None) == _lib.EINVAL
+    assert lib.kkt_apply(None, None, None) == _lib.EINVAL
+    assert lib.precond_apply(None, None, None) == _lib.EINVAL
+    assert lib.kkt_size(None) == 0
+    lib.kkt_destroy(None)
