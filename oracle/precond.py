@@ -98,8 +98,9 @@ def lower_bidiagonal_gram(n, diag, sub):
     return J @ J.T
 
 
-def coarse_operator_modes(p: Problem):
-    """S_hat_0 = Z^T S_hat Z (Sec. 3) for every sine mode: array (ny-1, nx-1, nc, nc).
+def coarse_operator_modes(p: Problem, q=None):
+    """S_hat_0 = Z^T S_hat Z (Sec. 3) for every sine mode: array (ny-1, nx-1, nc, nc),
+    or for the modes of row q only: (nx-1, nc, nc).
 
     In sine-mode space S_hat is block diagonal: mode lambda sees
     (1/h) T(d), T(d) = J_l J_l^T, J_l = lower bidiagonal(d, -1), d = sigma + dt*nu*lambda.
@@ -113,6 +114,8 @@ def coarse_operator_modes(p: Problem):
     G0 = Zt.T @ np.diag(np.r_[0.0, np.ones(nt - 1)]) @ Zt
     G1 = Zt.T @ (E + E.T) @ Zt
     d = p.sigma + p.dt * p.nu * mode_eigenvalues(p)
+    if q is not None:
+        d = d[q]
     d = d[..., None, None]
     return (d * d * G2 + G0 - d * G1) / p.h
 
@@ -127,9 +130,11 @@ def coarse_correction(p: Problem, r):
     Zt = coarse_time_basis(p)
     r0 = np.einsum("nc,nyx->cyx", Zt, r)
     r0_hat = dst2(p, r0)
-    S0 = coarse_operator_modes(p)                              # (my, mx, nc, nc)
-    rhs = np.moveaxis(r0_hat, 0, -1)[..., None]                # (my, mx, nc, 1)
-    c0_hat = np.moveaxis(np.linalg.solve(S0, rhs)[..., 0], -1, 0)
+    c0_hat = np.empty_like(r0_hat)
+    for q in range(p.my):                                       # one row of modes at a time
+        S0 = coarse_operator_modes(p, q)                        # (mx, nc, nc)
+        rhs = np.moveaxis(r0_hat[:, q, :], 0, -1)[..., None]    # (mx, nc, 1)
+        c0_hat[:, q, :] = np.moveaxis(np.linalg.solve(S0, rhs)[..., 0], -1, 0)
     c0 = idst2(p, c0_hat)
     return np.einsum("nc,cyx->nyx", Zt, c0)
 
