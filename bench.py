@@ -1,0 +1,190 @@
+#!/usr/bin/env python3
+"""Throughput of the two-level time-DD preconditioned KKT solve on one MI355X.
+
+One step = FGMRES(30) solves, from x0 = 0 to a 1e-8 relative residual, of the grid128
+workload at both of its regularisation parameters: 128x128 intervals (127^2 interior points),
+nt = 256, T = 1, nu = 1, omega in {1e-2, 1e-4}, 16 time subdomains with overlap 2, constant +
+linear coarse basis, seeded sine-mode target (12,387,072 KKT unknowns per problem).  The
+right-hand sides are resident in HBM before the timed region.  `value` is the float64 path;
+the float32-sweep path ("mixed": float32 sine-transform GEMMs and sweep state, float64 outer
+FGMRES, matvec and coarse level) is timed the same way and reported beside it.
+
+Prints one JSON line.  Extra objects:
+  roofline      the kernel class with the largest share of the float64 solve time, its
+                algorithmic bytes (or flops) over its HIP-event-timed launch durations,
+                against the MI355X peak; traffic from rocprofv3 counters when recorded
+  cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample of the same
+                workload (the first FGMRES iterations), scaled to a whole solve
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "KKT space-time unknowns solved/s to 1e-8 rel. residual, mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+WORKLOADS = ("grid128", "grid128_w4")
+# HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
+# calibration, for the kernel named in the roofline (None until measured for this build).
+TRAFFIC = None
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--rtol", type=float, default=1e-8)
+    ap.add_argument("--cpu-iters", type=int, default=4,
+                    help="FGMRES iterations of the CPU oracle sample (0: skip the CPU baseline)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the float32-sweep path")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+              "multi-GPU path.", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+    from paper_2305_04421_amd import KKTSolver, workloads as wl
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    probs = []
+    for name in WORKLOADS:
+        params, recipe = wl.config(name)
+        u0, ut = wl.data(params, recipe)
+        probs.append((name, params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
+    unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
+
+    def run_path(precision, steps, warmup, profile):
+        solvers = [KKTSolver(p, precision) for _, p, _, _ in probs]
+        fs = [S.rhs(u0, ut) for S, (_, _, u0, ut) in zip(solvers, probs)]
+        xs = [torch.zeros_like(f) for f in fs]
+        stats = []
+
+        def step():
+            out = []
+            for S, f, x in zip(solvers, fs, xs):
+                x.zero_()
+                _, st = S.solve(f, x=x, restart=args.restart, maxit=600, rtol=args.rtol)
+                if st["status"] != 0:
+                    raise RuntimeError(f"{precision} solve did not converge: {st}")
+                out.append(st)
+            return out
+
+        for _ in range(warmup):
+            step()
+        if profile:
+            for S in solvers:
+                S.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            stats = step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = None
+        if profile:
+            prof = {}
+            for S in solvers:
+                for k, v in S.profile_read().items():
+                    acc = prof.setdefault(k, dict(ms=0.0, launches=0, bytes=0.0, flops=0.0))
+                    for kk in acc:
+                        acc[kk] += v[kk]
+                S.profile(False)
+        for S in solvers:
+            S.close()
+        return dt, stats, prof
+
+    # float64 path: timed region with the per-launch HIP-event timer on
+    dt64, st64, prof64 = run_path("fp64", args.steps, args.warmup, profile=True)
+    value64 = args.steps * sum(unknowns) / dt64
+    result = {
+        "metric": METRIC, "value": value64, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt64 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "grid128: 127x127 interior x nt=256, T=1, nu=1, omega {1e-2, 1e-4}, "
+                               "16 time subdomains, overlap 2, constant+linear coarse basis, "
+                               "FGMRES(%d) to %g from x0=0" % (args.restart, args.rtol),
+                   "unknowns_per_step": sum(unknowns), "problems": list(WORKLOADS)},
+        "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st64)},
+        "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st64)},
+    }
+
+    # roofline of the dominant kernel class
+    dom = max(prof64, key=lambda k: prof64[k]["ms"])
+    d = prof64[dom]
+    total_ms = sum(v["ms"] for v in prof64.values())
+    if dom in ("sweep_rows", "sweep_cols"):
+        achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["fp64"], "unit": "TFLOP/s"}
+    else:
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = TRAFFIC
+    roof["kernel_class"] = dom
+    roof["launches"] = d["launches"]
+    roof["avg_launch_us"] = 1e3 * d["ms"] / max(d["launches"], 1)
+    roof["share_of_kernel_time"] = d["ms"] / total_ms if total_ms else None
+    roof["classes_ms_per_step"] = {k: v["ms"] / args.steps for k, v in prof64.items()}
+    result["roofline"] = roof
+
+    if not args.no_mixed:
+        dt32, st32, _ = run_path("fp32", args.steps, args.warmup, profile=False)
+        value32 = args.steps * sum(unknowns) / dt32
+        result["mixed"] = {
+            "dtype": "f32 sweeps+DST GEMMs, f64 FGMRES/matvec/coarse", "value": value32,
+            "ms_per_step": 1e3 * dt32 / args.steps, "ratio_vs_fp64": value32 / value64,
+            "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st32)},
+            "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st32)},
+        }
+
+    if args.cpu_iters > 0:
+        result["cpu_baseline"] = cpu_baseline(args, probs[0][1], st64[0]["iters"])
+
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def cpu_baseline(args, params, iters_full):
+    """The CPU oracle on a bounded sample: its first `cpu_iters` FGMRES iterations of the
+    omega=1e-2 problem, scaled to the iteration count of the full solve."""
+    import numpy as np
+    from oracle.problem import Problem
+    from oracle import operators as op, precond as pc, gmres as gm
+    from paper_2305_04421_amd import workloads as wl
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = None
+    p = Problem(**params).validate()
+    u0, ut = wl.data(params, wl.config("grid128")[1])
+    f = op.rhs(p, u0, ut)
+    t0 = time.perf_counter()
+    res = gm.gmres(lambda v: op.apply_K(p, v), lambda v: pc.apply_Pinv(p, v), f,
+                   restart=args.restart, maxit=args.cpu_iters, rtol=args.rtol)
+    dt = time.perf_counter() - t0
+    per_iter = dt / max(res.iterations, 1)
+    unknowns = p.size
+    return {"value": unknowns / (per_iter * iters_full), "unit": "unknowns/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"first {res.iterations} FGMRES({args.restart}) iterations of the grid128 omega=1e-2 "
+                      f"solve ({dt:.1f} s incl. the initial residual), scaled to the {iters_full} "
+                      f"iterations of the full solve; numpy float64 with {threads} BLAS threads"}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

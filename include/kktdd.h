@@ -133,6 +133,27 @@ int kkt_spatial_solve(kktdd_handle* h, const double* b, double* x, int32_t nslic
 int fgmres_solve(kktdd_handle* h, const double* f, double* x, int32_t restart, int32_t maxit,
                  double rtol, kktdd_stats* stats);
 
+/* Kernel classes of the per-launch timer below. */
+enum kktdd_kernel_class {
+  KKTDD_K_MATVEC = 0,      /* KKT matvec of Eq. (5), also the residual f - K x              */
+  KKTDD_K_SWEEP_ROWS = 1,  /* row-block sine-transform GEMMs of the sweeps (Eq. (13))       */
+  KKTDD_K_SWEEP_COLS = 2,  /* column-block sine-transform GEMMs of the sweeps               */
+  KKTDD_K_COARSE = 3,      /* coarse level of Eqs. (14)-(15) and the residual r - S_hat c   */
+  KKTDD_K_ARNOLDI = 4,     /* Gram-Schmidt passes and their reductions                      */
+  KKTDD_K_OTHER = 5,       /* solution update, norms, block scalings, diagnostics           */
+  KKTDD_K_COUNT = 6
+};
+
+/* Per-launch kernel timer.  enable != 0 clears the counters and brackets every later launch
+ * made through this handle with HIP events on the handle's stream; enable == 0 stops
+ * recording.  kkt_profile_read synchronises the stream and returns, for one class, the summed
+ * event time in milliseconds, the launch count, and the algorithmic HBM bytes and flops of
+ * those launches (bytes: vectors the kernels must read and write; flops: 2*m*m*m' per dense
+ * product with the unpadded grid sizes).  Any pointer may be NULL. */
+int kkt_profile(kktdd_handle* h, int enable);
+int kkt_profile_read(kktdd_handle* h, int kclass, double* ms, int64_t* launches, double* bytes,
+                     double* flops);
+
 /* Message of the calling thread's last failing call ("" if none). */
 const char* kkt_last_error(void);
 

@@ -119,6 +119,20 @@ class KKTSolver:
                                                  ns, float(shift)), "kkt_spatial_solve")
         return x
 
+    def profile(self, enable=True):
+        """Start (clearing the counters) or stop the per-launch kernel timer."""
+        _lib.check(_lib.load().kkt_profile(self._h, 1 if enable else 0), "kkt_profile")
+
+    def profile_read(self):
+        """{class: dict(ms, launches, bytes, flops)} summed over the launches timed so far."""
+        out = {}
+        for i, name in enumerate(_lib.KERNEL_CLASSES):
+            ms, n, b, f = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double(), ctypes.c_double()
+            _lib.check(_lib.load().kkt_profile_read(self._h, i, ctypes.byref(ms), ctypes.byref(n),
+                                                    ctypes.byref(b), ctypes.byref(f)), "kkt_profile_read")
+            out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value, flops=f.value)
+        return out
+
     def solve(self, f, x=None, restart=30, maxit=500, rtol=1e-8):
         """FGMRES(restart) from x (zero if None); returns (x, stats dict)."""
         import torch

@@ -33,6 +33,55 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   return set_error(KKTDD_EHIP, buf);
 }
 
+// ---- per-launch timer ------------------------------------------------------------------
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // events are created once and reused
+  size_t used = 0;
+  struct Rec { int cls; size_t ev; double bytes, flops; };
+  std::vector<Rec> recs;
+  size_t open_ev = 0;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+namespace {
+thread_local Prof* t_prof = nullptr;
+}
+
+void prof_begin(int kclass, hipStream_t s) {
+  (void)kclass;
+  if (!t_prof || !t_prof->on) return;
+  hipEvent_t e = t_prof->next();
+  if (!e) return;
+  t_prof->open_ev = t_prof->used - 1;
+  (void)hipEventRecord(e, s);
+}
+
+void prof_end(int kclass, hipStream_t s, double bytes, double flops) {
+  if (!t_prof || !t_prof->on) return;
+  hipEvent_t e = t_prof->next();
+  if (!e) return;
+  (void)hipEventRecord(e, s);
+  t_prof->recs.push_back({kclass, t_prof->open_ev, bytes, flops});
+}
+
+long long prof_mark() { return (t_prof && t_prof->on) ? (long long)t_prof->recs.size() : -1; }
+
+void prof_add_bytes(long long record, double bytes) {
+  if (!t_prof || record < 0 || record >= (long long)t_prof->recs.size()) return;
+  t_prof->recs[(size_t)record].bytes += bytes;
+}
+
 }  // namespace kktdd
 
 using namespace kktdd;
@@ -63,6 +112,7 @@ struct kktdd_handle {
   double *V = nullptr, *Zw = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
   int* gate = nullptr;
   double* host_hcol = nullptr;                 // pinned
+  Prof prof;
 
   const void* Sx() const { return prob.precision == KKTDD_FP32 ? (const void*)Sx32 : (const void*)Sx64; }
   const void* Sy() const { return prob.precision == KKTDD_FP32 ? (const void*)Sy32 : (const void*)Sy64; }
@@ -72,6 +122,13 @@ struct kktdd_handle {
 };
 
 namespace {
+
+// Makes the handle's timer current for the calling thread during one entry point.
+struct ProfScope {
+  Prof* saved;
+  explicit ProfScope(kktdd_handle* H) : saved(t_prof) { t_prof = H ? &H->prof : nullptr; }
+  ~ProfScope() { t_prof = saved; }
+};
 
 template <typename T>
 int dalloc(kktdd_handle* h, T** p, size_t count) {
@@ -421,17 +478,20 @@ void kkt_destroy(kktdd_handle* H) {
   for (void* p : H->allocations) (void)hipFree(p);
   if (H->host_sums) (void)hipHostFree(H->host_sums);
   if (H->host_hcol) (void)hipHostFree(H->host_hcol);
+  for (hipEvent_t e : H->prof.pool) (void)hipEventDestroy(e);
   delete H;
 }
 
 size_t kkt_size(const kktdd_handle* H) { return H ? (size_t)(3 * H->g.P) : 0; }
 
 int kkt_rhs(kktdd_handle* H, const double* u0, const double* utilde, double* f) {
+  ProfScope ps(H);
   if (!H || !u0 || !utilde || !f) return set_error(KKTDD_EINVAL, "NULL argument");
   return launch_rhs(H->g, u0, utilde, f, H->stream);
 }
 
 int kkt_apply(kktdd_handle* H, const double* x, double* y) {
+  ProfScope ps(H);
   if (!H || !x || !y) return set_error(KKTDD_EINVAL, "NULL argument");
   if (x == y) return set_error(KKTDD_EINVAL, "x and y must not alias");
   const Geom& g = H->g;
@@ -440,6 +500,7 @@ int kkt_apply(kktdd_handle* H, const double* x, double* y) {
 }
 
 int precond_apply(kktdd_handle* H, const double* r, double* z) {
+  ProfScope ps(H);
   if (!H || !r || !z) return set_error(KKTDD_EINVAL, "NULL argument");
   if (r == z) return set_error(KKTDD_EINVAL, "r and z must not alias");
   const Geom& g = H->g;
@@ -449,6 +510,7 @@ int precond_apply(kktdd_handle* H, const double* r, double* z) {
 }
 
 int kkt_spatial_solve(kktdd_handle* H, const double* b, double* x, int32_t nslices, double shift) {
+  ProfScope ps(H);
   if (!H || !b || !x) return set_error(KKTDD_EINVAL, "NULL argument");
   if (nslices < 0 || !(shift > 0.0) || !std::isfinite(shift)) return set_error(KKTDD_EINVAL, "bad nslices or shift");
   if (nslices == 0) return KKTDD_OK;
@@ -498,6 +560,7 @@ int kkt_spatial_solve(kktdd_handle* H, const double* b, double* x, int32_t nslic
 int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, int32_t maxit,
                  double rtol, kktdd_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
+  ProfScope ps(H);
   if (!H || !f || !x) return set_error(KKTDD_EINVAL, "NULL argument");
   if (f == x) return set_error(KKTDD_EINVAL, "f and x must not alias");
   if (restart < 1 || restart > 31 || maxit < 0 || !(rtol > 0.0))
@@ -605,6 +668,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       if (int e = launch_arnoldi_finish(j, nullptr, sums2, nullptr, H->gate, H->hcol, H->vinv,
                                         kReorthEta, 2, s)) return e;
       // pass C (only if the gate is set): w -= V h2; ||w2||
+      const long long passC = prof_mark();
       if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 0,
                                     H->partials, kRedBlocks, H->gate, s)) return e;
       if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums3, s)) return e;
@@ -614,7 +678,10 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
                              hipMemcpyDeviceToHost, s));
       KKT_HIP(hipStreamSynchronize(s));
       const double* hc = H->host_hcol;
-      if (hc[j + 2] != 0.0) ++st.reorth;
+      if (hc[j + 2] != 0.0) {
+        ++st.reorth;
+        prof_add_bytes(passC, (double)(nv + 2) * n3 * 8.0);   // the gated pass ran
+      }
       for (int i = 0; i <= j + 1; ++i) {
         if (!std::isfinite(hc[i])) {
           const double z3[3] = {NAN, NAN, NAN};
@@ -656,6 +723,39 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
                                        1.0 / (g.omega * g.h), x, s)) return e;
     (void)breakdown;
   }
+}
+
+int kkt_profile(kktdd_handle* H, int enable) {
+  if (!H) return set_error(KKTDD_EINVAL, "NULL handle");
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  if (enable) {
+    H->prof.recs.clear();
+    H->prof.used = 0;
+  }
+  H->prof.on = enable != 0;
+  return KKTDD_OK;
+}
+
+int kkt_profile_read(kktdd_handle* H, int kclass, double* ms, int64_t* launches, double* bytes,
+                     double* flops) {
+  if (!H || kclass < 0 || kclass >= KKTDD_K_COUNT) return set_error(KKTDD_EINVAL, "bad handle or class");
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  double t = 0.0, b = 0.0, f = 0.0;
+  int64_t n = 0;
+  for (const Prof::Rec& r : H->prof.recs) {
+    if (r.cls != kclass) continue;
+    float e = 0.0f;
+    KKT_HIP(hipEventElapsedTime(&e, H->prof.pool[r.ev], H->prof.pool[r.ev + 1]));
+    t += e;
+    b += r.bytes;
+    f += r.flops;
+    ++n;
+  }
+  if (ms) *ms = t;
+  if (launches) *launches = n;
+  if (bytes) *bytes = b;
+  if (flops) *flops = f;
+  return KKTDD_OK;
 }
 
 const char* kkt_last_error(void) { return g_last_error.c_str(); }

@@ -139,8 +139,10 @@ k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict
 int launch_restrict(const Geom& g, const double* rw, const double* dscale, double* r0,
                     hipStream_t s) {
   const dim3 grid((g.nxy + kBlock - 1) / kBlock, g.nd);
+  prof_begin(KKTDD_K_COARSE, s);
   hipLaunchKernelGGL(k_restrict, grid, dim3(kBlock), 0, s, g, rw, dscale, r0);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 8.0 * g.P + 8.0 * g.nc * g.nxy, 0.0);
   return 0;
 }
 
@@ -154,18 +156,22 @@ int launch_coarse_factor(const Geom& g, const double* G2, const double* G0, cons
 }
 
 int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStream_t s) {
+  prof_begin(KKTDD_K_COARSE, s);
   hipLaunchKernelGGL(k_coarse_solve, dim3((g.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
                      fac, xhat);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 8.0 * g.nxy * g.nc * (2.0 * g.nb + 2.0), 0.0);
   return 0;
 }
 
 int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
                           const double* c0, const double* Dc0, const double* DDc0,
                           double* rprime, hipStream_t s) {
+  prof_begin(KKTDD_K_COARSE, s);
   hipLaunchKernelGGL(k_residual_prime, dim3((unsigned)((g.P + kBlock - 1) / kBlock)),
                      dim3(kBlock), 0, s, g, rw, dscale, c0, Dc0, DDc0, rprime);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 16.0 * g.P, 0.0);
   return 0;
 }
 

@@ -299,42 +299,48 @@ int allow_lds(F* kernel, size_t lds) {
   return 0;
 }
 
+// Algorithmic flops of one launch: 2*my*mx*mx per right product, 2*my*my*mx per left product.
 template <typename T, int TPW>
-int rows_t(const Geom& g, const RowArgs<T>& a, int nslices, int nw, hipStream_t s) {
+int rows_t(const Geom& g, const RowArgs<T>& a, int nslices, int nw, int kclass, hipStream_t s) {
   const size_t lds = (size_t)16 * (g.Mx + 1) * sizeof(T);
   if (int e = allow_lds(k_rows<T, TPW>, lds)) return e;
+  const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
+  prof_begin(kclass, s);
   hipLaunchKernelGGL((k_rows<T, TPW>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
+  prof_end(kclass, s, 0.0, 2.0 * ngemm * nslices * (double)g.my * g.mx * g.mx);
   return 0;
 }
 
 template <typename T, int TPW>
-int cols_t(const Geom& g, const ColArgs<T>& a, int nslices, int nw, hipStream_t s) {
+int cols_t(const Geom& g, const ColArgs<T>& a, int nslices, int nw, int kclass, hipStream_t s) {
   const size_t lds = (size_t)g.My * 17 * sizeof(T);
   if (int e = allow_lds(k_cols<T, TPW>, lds)) return e;
+  prof_begin(kclass, s);
   hipLaunchKernelGGL((k_cols<T, TPW>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
+  prof_end(kclass, s, 0.0, 2.0 * (1 + a.two) * nslices * (double)g.my * g.my * g.mx);
   return 0;
 }
 
 template <typename T>
-int rows(const Geom& g, const RowArgs<T>& a, int nslices, hipStream_t s) {
+int rows(const Geom& g, const RowArgs<T>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.Mx);
   const int tpw = (g.Mx / 16 + nw - 1) / nw;
-  if (tpw <= 1) return rows_t<T, 1>(g, a, nslices, nw, s);
-  if (tpw <= 2) return rows_t<T, 2>(g, a, nslices, nw, s);
-  if (tpw <= 4) return rows_t<T, 4>(g, a, nslices, nw, s);
-  return rows_t<T, 8>(g, a, nslices, nw, s);
+  if (tpw <= 1) return rows_t<T, 1>(g, a, nslices, nw, kclass, s);
+  if (tpw <= 2) return rows_t<T, 2>(g, a, nslices, nw, kclass, s);
+  if (tpw <= 4) return rows_t<T, 4>(g, a, nslices, nw, kclass, s);
+  return rows_t<T, 8>(g, a, nslices, nw, kclass, s);
 }
 
 template <typename T>
-int cols(const Geom& g, const ColArgs<T>& a, int nslices, hipStream_t s) {
+int cols(const Geom& g, const ColArgs<T>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.My);
   const int tpw = (g.My / 16 + nw - 1) / nw;
-  if (tpw <= 1) return cols_t<T, 1>(g, a, nslices, nw, s);
-  if (tpw <= 2) return cols_t<T, 2>(g, a, nslices, nw, s);
-  if (tpw <= 4) return cols_t<T, 4>(g, a, nslices, nw, s);
-  return cols_t<T, 8>(g, a, nslices, nw, s);
+  if (tpw <= 1) return cols_t<T, 1>(g, a, nslices, nw, kclass, s);
+  if (tpw <= 2) return cols_t<T, 2>(g, a, nslices, nw, kclass, s);
+  if (tpw <= 4) return cols_t<T, 4>(g, a, nslices, nw, kclass, s);
+  return cols_t<T, 8>(g, a, nslices, nw, kclass, s);
 }
 
 template <typename T>
@@ -354,16 +360,16 @@ int spatial_solve_t(const Geom& g, const void* Sx, const void* Sy, const void* i
   r1.rin = b;
   r1.g2_out = static_cast<T*>(w1);
   r1.g2_stride = MM;
-  if (int e = rows<T>(g, r1, nslices, s)) return e;
+  if (int e = rows<T>(g, r1, nslices, KKTDD_K_OTHER, s)) return e;
   ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(w1), MM,
                static_cast<const T*>(invlam), 1, static_cast<T*>(w2), MM};
-  if (int e = cols<T>(g, c, nslices, s)) return e;
+  if (int e = cols<T>(g, c, nslices, KKTDD_K_OTHER, s)) return e;
   RowArgs<T> r2 = row_args<T>(Sx);
   r2.g1_in = static_cast<const T*>(w2);
   r2.g1_stride = MM;
   r2.out_mode = OUT_PLAIN;
   r2.out64 = x;
-  return rows<T>(g, r2, nslices, s);
+  return rows<T>(g, r2, nslices, KKTDD_K_OTHER, s);
 }
 
 // RASQ sweeps (Eq. (13)) of all subdomains in lockstep.  Subdomain s (0-based) covers the
@@ -396,8 +402,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.rin = rprime;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, s)) return e;
-    if (int e = cols<T>(g, c, nd, s)) return e;
+    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   // junction: y_{L-1} from the last solve; adjoint right-hand side h*y_{L-1}
   {
@@ -407,8 +413,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.b_mode = B_H_Y;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, s)) return e;
-    if (int e = cols<T>(g, c, nd, s)) return e;
+    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   // adjoint sweep: x_j = D^{-1}(h y_j + x_{j+1}); owned x_{j+1} written with the coarse part
   for (int j = L - 2; j >= 0; --j) {
@@ -425,8 +431,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.ybuf_stride = ystride;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, s)) return e;
-    if (int e = cols<T>(g, c, nd, s)) return e;
+    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   RowArgs<T> r = row_args<T>(Sx);
   r.g1_in = Ubuf;
@@ -436,7 +442,7 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
   r.c0 = c0;
   r.g1_step = 0;
   r.b_mode = B_NONE;
-  return rows<T>(g, r, nd, s);
+  return rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s);
 }
 
 }  // namespace
@@ -466,23 +472,23 @@ int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const d
   r.rin = r0;
   r.g2_out = tmp;
   r.g2_stride = MM;
-  if (int e = rows<double>(g, r, g.nc, s)) return e;
+  if (int e = rows<double>(g, r, g.nc, KKTDD_K_COARSE, s)) return e;
   ColArgs<double> c{Sy, tmp, MM, nullptr, 0, rhat, MM};
-  return cols<double>(g, c, g.nc, s);
+  return cols<double>(g, c, g.nc, KKTDD_K_COARSE, s);
 }
 
 int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
                        double* c0, double* tmp, double norm, hipStream_t s) {
   const long long MM = g.padded();
   ColArgs<double> c{Sy, chat, MM, nullptr, 0, tmp, MM};
-  if (int e = cols<double>(g, c, g.nc, s)) return e;
+  if (int e = cols<double>(g, c, g.nc, KKTDD_K_COARSE, s)) return e;
   RowArgs<double> r = row_args<double>(Sx);
   r.g1_in = tmp;
   r.g1_stride = MM;
   r.g1_scale = norm;
   r.out_mode = OUT_PLAIN;
   r.out64 = c0;
-  return rows<double>(g, r, g.nc, s);
+  return rows<double>(g, r, g.nc, KKTDD_K_COARSE, s);
 }
 
 }  // namespace kktdd

@@ -46,6 +46,13 @@ inline int round_up16(int v) { return (v + 15) / 16 * 16; }
 int hip_fail(hipError_t e, const char* what, const char* file, int line);
 int set_error(int code, const std::string& msg);
 
+// Per-launch timing (enabled per handle through kkt_profile): no-ops unless the calling
+// thread is inside an entry point of a handle whose timer is on.
+void prof_begin(int kclass, hipStream_t s);
+void prof_end(int kclass, hipStream_t s, double bytes, double flops);
+long long prof_mark();                          // index of the next record (-1: timer off)
+void prof_add_bytes(long long record, double bytes);
+
 // ---- stencil.hip: KKT matvec, right-hand side, block scalings, D_sigma stencil ----------
 // y = K [su*xu; sz*xz; sw*xw] (Eq. (5)); su and sz are further multiplied by the optional
 // device scalar *dscale (nullptr: 1).  If f != nullptr, y = f - K x instead.

@@ -215,6 +215,7 @@ int launch_multidot(long long n, const double* V, long long ldv, int nv, const d
                     hipStream_t s) {
   (void)vinv;
   const dim3 grid(nblocks), block(kBlock);
+  prof_begin(KKTDD_K_ARNOLDI, s);
   if (nv <= 8)
     hipLaunchKernelGGL((k_multidot<8>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
   else if (nv <= 16)
@@ -224,6 +225,7 @@ int launch_multidot(long long n, const double* V, long long ldv, int nv, const d
   else
     return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (nv + 1) * n, 0.0);
   return 0;
 }
 
@@ -231,6 +233,7 @@ int launch_update_dot(long long n, const double* V, long long ldv, int nv, const
                       const double* coef, const double* w, double* wout, int want_dots,
                       double* partials, int nblocks, const int* gate, hipStream_t s) {
   const dim3 grid(nblocks), block(kBlock);
+  prof_begin(KKTDD_K_ARNOLDI, s);
   if (nv <= 8)
     hipLaunchKernelGGL((k_update_dot<8>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
                        want_dots, partials, gate);
@@ -243,22 +246,28 @@ int launch_update_dot(long long n, const double* V, long long ldv, int nv, const
   else
     return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
   KKT_HIP(hipGetLastError());
+  // a gated pass counts its bytes only once the host knows it ran
+  prof_end(KKTDD_K_ARNOLDI, s, gate ? 0.0 : 8.0 * (nv + 2) * n, 0.0);
   return 0;
 }
 
 int launch_reduce_partials(const double* partials, int nblocks, int nsums, double* out,
                            hipStream_t s) {
+  prof_begin(KKTDD_K_ARNOLDI, s);
   hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, partials, nblocks, nsums, out);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * nblocks * nsums, 0.0);
   return 0;
 }
 
 int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const double* sums3,
                           int* gate, double* hcol, double* vinv, double eta, int stage,
                           hipStream_t s) {
+  prof_begin(KKTDD_K_ARNOLDI, s);
   hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, s, j, sums1, sums2, sums3, gate, hcol,
                      vinv, eta, stage);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 0.0, 0.0);
   return 0;
 }
 
@@ -268,16 +277,20 @@ int launch_update_solution(const Geom& g, const double* V, long long ldv, const 
   const long long n3 = 3 * g.P;
   long long nb = (n3 + kBlock - 1) / kBlock;
   if (nb > 8192) nb = 8192;
+  prof_begin(KKTDD_K_OTHER, s);
   hipLaunchKernelGGL(k_update_solution, dim3((unsigned)nb), dim3(kBlock), 0, s, g, V, ldv, Zw, ldz,
                      nv, y, vinv, su, sz, x);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_OTHER, s, 8.0 * g.P * (2.0 * nv + nv + 6.0), 0.0);
   return 0;
 }
 
 int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
                         hipStream_t s) {
+  prof_begin(KKTDD_K_OTHER, s);
   hipLaunchKernelGGL(k_sumsq_blocks, dim3(nblocks), dim3(kBlock), 0, s, g, r, partials);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_OTHER, s, 24.0 * g.P, 0.0);
   return 0;
 }
 

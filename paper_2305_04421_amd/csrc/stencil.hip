@@ -121,23 +121,29 @@ int launch_kkt_apply(const Geom& g, const double* xu, const double* xz, const do
   int tb = 16;
   while (tb > 1 && (long long)nchunks * ((g.nt + tb - 1) / tb) < 2048) tb /= 2;
   const int ntb = (g.nt + tb - 1) / tb;
+  prof_begin(KKTDD_K_MATVEC, s);
   hipLaunchKernelGGL(k_kkt_apply, dim3(nchunks * ntb), dim3(kBlock), 0, s, g, xu, xz, xw, su, sz,
                      sw, dscale, f, yu, yz, yw, tb, nchunks);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_MATVEC, s, (f ? 72.0 : 48.0) * g.P, 0.0);
   return 0;
 }
 
 int launch_rhs(const Geom& g, const double* u0, const double* ut, double* f, hipStream_t s) {
+  prof_begin(KKTDD_K_OTHER, s);
   hipLaunchKernelGGL(k_rhs, dim3(blocks_for(g.P)), dim3(kBlock), 0, s, g, u0, ut, f);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_OTHER, s, 32.0 * g.P, 0.0);
   return 0;
 }
 
 int launch_scale(long long n, const double* in, double a, const double* dscale, double* out,
                  hipStream_t s) {
   if (n == 0) return 0;
+  prof_begin(KKTDD_K_OTHER, s);
   hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, in, a, dscale, out);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_OTHER, s, 16.0 * n, 0.0);
   return 0;
 }
 
@@ -145,9 +151,11 @@ int launch_apply_D(const Geom& g, const double* in, double* out, int nslices, do
                    hipStream_t s) {
   const long long n = (long long)nslices * g.nxy;
   if (n == 0) return 0;
+  prof_begin(KKTDD_K_COARSE, s);
   hipLaunchKernelGGL(k_apply_D, dim3(blocks_for(n)), dim3(kBlock), 0, s, g, in, out, nslices,
                      shift);
   KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 16.0 * n, 0.0);
   return 0;
 }
 
