@@ -133,6 +133,17 @@ int kkt_spatial_solve(kktdd_handle* h, const double* b, double* x, int32_t nslic
 int fgmres_solve(kktdd_handle* h, const double* f, double* x, int32_t restart, int32_t maxit,
                  double rtol, kktdd_stats* stats);
 
+/* Solve n independent problems, each by fgmres_solve with the same restart, maxit and rtol.
+ * hs: n distinct handles (grid sizes, nt and parameters may all differ); f[i], x[i]: device
+ * vectors of kkt_size(hs[i]) doubles (x[i] is the initial guess, then the iterate).  The
+ * problems run concurrently, each on a private stream ordered after the work already queued
+ * on its handle's stream; the call returns when all are done.  stats: NULL or n entries.
+ * Returns KKTDD_OK if every problem converged, KKTDD_NOT_CONVERGED if some did not, else the
+ * most severe error (message names the problem). */
+int kkt_solve_batched(int32_t n, kktdd_handle* const* hs, const double* const* f,
+                      double* const* x, int32_t restart, int32_t maxit, double rtol,
+                      kktdd_stats* stats);
+
 /* Kernel classes of the per-launch timer below. */
 enum kktdd_kernel_class {
   KKTDD_K_MATVEC = 0,      /* KKT matvec of Eq. (5), also the residual f - K x              */

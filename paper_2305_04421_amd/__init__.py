@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import KKTDDError  # noqa: F401
 
-__all__ = ["KKTSolver", "KKTDDError", "validate", "memory_plan", "library_path"]
+__all__ = ["KKTSolver", "KKTDDError", "validate", "memory_plan", "library_path", "solve_batched"]
 
 
 def library_path():
@@ -143,3 +143,20 @@ class KKTSolver:
                                         int(restart), int(maxit), float(rtol), ctypes.byref(st))
         _lib.check(code, "fgmres_solve")
         return x, st.as_dict()
+
+
+def solve_batched(solvers, fs, xs=None, restart=30, maxit=500, rtol=1e-8):
+    """Solve independent problems concurrently (kkt_solve_batched); returns (xs, [stats])."""
+    import torch
+    n = len(solvers)
+    if len(fs) != n or (xs is not None and len(xs) != n):
+        raise ValueError("solvers, fs and xs must have the same length")
+    if xs is None:
+        xs = [torch.zeros(S.size, dtype=torch.float64, device="cuda") for S in solvers]
+    hs = (ctypes.c_void_p * n)(*[S._h.value for S in solvers])
+    fp = (ctypes.c_void_p * n)(*[_ptr(f, S.size, "f").value for S, f in zip(solvers, fs)])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x, S.size, "x").value for S, x in zip(solvers, xs)])
+    st = (_lib.Stats * n)()
+    code = _lib.load().kkt_solve_batched(n, hs, fp, xp, int(restart), int(maxit), float(rtol), st)
+    _lib.check(code, "kkt_solve_batched")
+    return xs, [s.as_dict() for s in st]

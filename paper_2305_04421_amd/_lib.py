@@ -18,7 +18,7 @@ FP64, FP32 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
 
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_rhs",
-            "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_profile",
+            "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
             "kkt_profile_read", "kkt_last_error")
 
 # enum kktdd_kernel_class
@@ -71,13 +71,16 @@ def load():
     lib.precond_apply.argtypes = [vp, vp, vp]
     lib.kkt_spatial_solve.argtypes = [vp, vp, vp, i32, dbl]
     lib.fgmres_solve.argtypes = [vp, vp, vp, i32, i32, dbl, ctypes.POINTER(Stats)]
+    lib.kkt_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      i32, i32, dbl, ctypes.POINTER(Stats)]
     lib.kkt_profile.argtypes = [vp, ctypes.c_int]
     lib.kkt_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.kkt_last_error.argtypes = []
     lib.kkt_last_error.restype = ctypes.c_char_p
     for name in ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_rhs", "kkt_apply",
-                 "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_profile", "kkt_profile_read"):
+                 "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
+                 "kkt_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <string>
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 #include "internal.h"
@@ -171,8 +172,8 @@ Geom make_geom(const kktdd_problem& p) {
   Geom g{};
   g.mx = p.nx - 1;
   g.my = p.ny - 1;
-  g.Mx = round_up16(g.mx);
-  g.My = round_up16(g.my);
+  g.Mx = pad_extent(g.mx);
+  g.My = pad_extent(g.my);
   g.nt = p.nt;
   g.nxy = g.mx * g.my;
   g.P = (long long)g.nt * g.nxy;
@@ -192,6 +193,10 @@ Geom make_geom(const kktdd_problem& p) {
   return g;
 }
 
+// Leading dimension of the Krylov basis: 3P rounded up to 64 doubles, so every basis vector
+// starts 512-byte aligned (the Arnoldi kernels stream them with 16-byte loads).
+long long krylov_ld(const Geom& g) { return (3 * g.P + 63) / 64 * 64; }
+
 struct Plan {
   size_t tables, sweeps, coarse, krylov;
   size_t total() const { return tables + sweeps + coarse + krylov; }
@@ -209,7 +214,7 @@ Plan plan(const Geom& g, int precision, int R) {
                (size_t)g.nxy * g.nc * (hb + 1) * 8;
   }
   p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
-  if (R > 0) p.krylov = ((size_t)(R + 1) * 3 + (size_t)R) * (size_t)g.P * 8 + 4096;
+  if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
   return p;
 }
 
@@ -370,13 +375,13 @@ int ensure_krylov(kktdd_handle* H, int R) {
   H->R = 0;
   size_t free_b = 0, total_b = 0;
   KKT_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t need = ((size_t)(R + 1) * 3 + (size_t)R) * (size_t)g.P * 8;
+  const size_t need = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8;
   if (need > free_b) {
     char buf[200];
     std::snprintf(buf, sizeof buf, "Krylov basis for restart %d needs %zu bytes, %zu free", R, need, free_b);
     return set_error(KKTDD_ENOMEM, buf);
   }
-  if (int e = dalloc(H, &H->V, (size_t)(R + 1) * 3 * g.P)) return e;
+  if (int e = dalloc(H, &H->V, (size_t)(R + 1) * (size_t)krylov_ld(g))) return e;
   if (int e = dalloc(H, &H->Zw, (size_t)R * g.P)) return e;
   H->R = R;
   return 0;
@@ -607,7 +612,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   }
   const double tol = rtol * fnorm;
   const int R = restart;
-  const long long ldv = n3;
+  const long long ldv = krylov_ld(g);
   double* V = H->V;
   double* Zw = H->Zw;
   std::vector<double> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
@@ -723,6 +728,68 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
                                        1.0 / (g.omega * g.h), x, s)) return e;
     (void)breakdown;
   }
+}
+
+int kkt_solve_batched(int32_t n, kktdd_handle* const* hs, const double* const* f,
+                      double* const* x, int32_t restart, int32_t maxit, double rtol,
+                      kktdd_stats* stats) {
+  if (n < 0 || (n > 0 && (!hs || !f || !x))) return set_error(KKTDD_EINVAL, "bad batch arguments");
+  if (n == 0) return KKTDD_OK;
+  for (int i = 0; i < n; ++i) {
+    if (!hs[i] || !f[i] || !x[i]) return set_error(KKTDD_EINVAL, "NULL handle or vector in batch");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return set_error(KKTDD_EINVAL, "a handle appears twice in the batch");
+  }
+  // Every problem runs on a private stream of its own host thread, ordered after the work
+  // already queued on its handle's stream and before anything queued there later.
+  std::vector<hipStream_t> priv(n, nullptr), orig(n, nullptr);
+  std::vector<hipEvent_t> ev(n, nullptr);
+  int rc = KKTDD_OK;
+  for (int i = 0; i < n && rc == KKTDD_OK; ++i) {
+    orig[i] = hs[i]->stream;
+    hipError_t e = hipStreamCreateWithFlags(&priv[i], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev[i], orig[i]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(priv[i], ev[i], 0);
+    if (e != hipSuccess) rc = hip_fail(e, "batch stream setup", __FILE__, __LINE__);
+  }
+  std::vector<int> codes(n, KKTDD_OK);
+  std::vector<std::string> msgs(n);
+  if (rc == KKTDD_OK) {
+    int device = 0;
+    (void)hipGetDevice(&device);
+    std::vector<std::thread> pool;
+    pool.reserve(n);
+    for (int i = 0; i < n; ++i) {
+      pool.emplace_back([&, i]() {
+        (void)hipSetDevice(device);
+        hs[i]->stream = priv[i];
+        codes[i] = fgmres_solve(hs[i], f[i], x[i], restart, maxit, rtol, stats ? stats + i : nullptr);
+        if (codes[i] < 0) msgs[i] = g_last_error;
+      });
+    }
+    for (auto& t : pool) t.join();
+  }
+  for (int i = 0; i < n; ++i) {
+    if (priv[i]) {
+      if (ev[i] && hipEventRecord(ev[i], priv[i]) == hipSuccess) (void)hipStreamWaitEvent(orig[i], ev[i], 0);
+      (void)hipStreamSynchronize(priv[i]);
+      (void)hipStreamDestroy(priv[i]);
+    }
+    if (ev[i]) (void)hipEventDestroy(ev[i]);
+    hs[i]->stream = orig[i];
+  }
+  if (rc != KKTDD_OK) return rc;
+  int worst = KKTDD_OK;
+  for (int i = 0; i < n; ++i) {
+    if (codes[i] < 0 && (worst >= 0 || codes[i] < worst)) {
+      worst = codes[i];
+      g_last_error = "problem " + std::to_string(i) + ": " + msgs[i];
+    } else if (codes[i] == KKTDD_NOT_CONVERGED && worst == KKTDD_OK) {
+      worst = KKTDD_NOT_CONVERGED;
+    }
+  }
+  return worst;
 }
 
 int kkt_profile(kktdd_handle* H, int enable) {

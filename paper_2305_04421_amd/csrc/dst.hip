@@ -20,6 +20,8 @@
 // f64 (checked on gfx950).  The sine matrices are read straight from
 // L2 (they are shared by every workgroup) using their symmetry so that each MFMA operand load
 // is four 64-byte or 128-byte row segments; the other operand sits in LDS.
+#include <cstdlib>
+
 #include "internal.h"
 
 namespace kktdd {
@@ -44,6 +46,70 @@ __device__ inline v4f mfma16(float a, float b, v4f c) {
 template <typename T> __device__ inline int acc_row(int lk, int r);
 template <> __device__ inline int acc_row<float>(int lk, int r) { return 4 * lk + r; }
 template <> __device__ inline int acc_row<double>(int lk, int r) { return lk + 4 * r; }
+
+// ---- tile GEMMs ------------------------------------------------------------------------
+// Work split inside a workgroup: the M/16 column (or row) tiles of a 16-wide block are dealt
+// to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
+// that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
+// kPD k-steps ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.
+constexpr int kPD = 4;
+
+// acc[t] += A (16 x M, in LDS with row stride lda) * S(:, tile wave + t*nw), S symmetric M x M.
+template <typename T, int TPW, typename Acc>
+__device__ inline void gemm_right(const T* A, int lda, const T* __restrict__ S, int M, int wave,
+                                  int nw, int li, int lk, Acc (&acc)[TPW]) {
+  const T* Sp = S + (long long)lk * M + wave * 16 + li;
+  const long long tstride = (long long)nw * 16;
+  T bq[kPD][TPW];
+#pragma unroll
+  for (int p = 0; p < kPD; ++p)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+  const int nks = M >> 2;
+  for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+#pragma unroll
+    for (int p = 0; p < kPD; ++p) {
+      const int ks = ks0 + p;
+      const T a = A[li * lda + 4 * ks + lk];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
+      const int kn = ks + kPD;
+      if (kn < nks) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+      }
+    }
+  }
+}
+
+// acc[t] += S(row tile wave + t*nw, :) * B (M x 16, in LDS with row stride ldb).
+template <typename T, int TPW, typename Acc>
+__device__ inline void gemm_left(const T* __restrict__ S, const T* B, int ldb, int M, int wave,
+                                 int nw, int li, int lk, Acc (&acc)[TPW]) {
+  // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
+  const T* Sp = S + (long long)lk * M + wave * 16 + li;
+  const long long tstride = (long long)nw * 16;
+  T aq[kPD][TPW];
+#pragma unroll
+  for (int p = 0; p < kPD; ++p)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+  const int nks = M >> 2;
+  for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+#pragma unroll
+    for (int p = 0; p < kPD; ++p) {
+      const int ks = ks0 + p;
+      const T b = B[(4 * ks + lk) * ldb + li];
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
+      const int kn = ks + kPD;
+      if (kn < nks) {
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+      }
+    }
+  }
+}
 
 // ---- row kernel ------------------------------------------------------------------------
 // One workgroup = 16 rows of one slice.  Optional GEMM1 (y = g1_scale * U S_x) with its
@@ -73,7 +139,7 @@ struct RowArgs {
 };
 
 template <typename T, int TPW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_rows(Geom g, RowArgs<T> a) {
   using acc_t = typename AccT<T>::type;
   extern __shared__ unsigned char smem_raw[];
@@ -83,33 +149,48 @@ k_rows(Geom g, RowArgs<T> a) {
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ntiles = Mx >> 4;
   acc_t acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
+
+  // node of a sweep step in this subdomain (0-based subdomain s): first = s*k + 1 - delta
+  const int first = s * g.k + 1 - g.delta;
+
+  // Right-hand-side operands of b, fetched before GEMM1 so their latency hides behind it.
+  T pre[TPW][4];
+  if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
+    const int bnode = first + a.b_step;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int col = (wave + t * nw) * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = rb * 16 + acc_row<T>(lk, r);
+        const bool in = row < g.my && col < g.mx;
+        T v = 0;
+        if (a.b_mode == B_RPRIME_PLUS_Y) {
+          if (in && bnode >= 1) v = (T)a.rin[(long long)(bnode - 1) * g.nxy + row * g.mx + col];
+        } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
+          v = a.ybuf_in[s * a.ybuf_stride + (long long)row * Mx + col];
+        } else if (in) {
+          v = (T)a.rin[(long long)s * g.nxy + row * g.mx + col];
+        }
+        pre[t][r] = v;
+      }
+    }
+  }
 
   // ---- GEMM1: y = U S_x ------------------------------------------------------------------
   if (a.g1_in) {
     const T* src = a.g1_in + s * a.g1_stride + (long long)rb * 16 * Mx;
     for (int e = threadIdx.x; e < 16 * Mx; e += nthr) A[(e / Mx) * lda + e % Mx] = src[e];
     __syncthreads();
-#pragma unroll 8
-    for (int k0 = 0; k0 < Mx; k0 += 4) {
-      const T av = A[li * lda + k0 + lk];
-#pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * nw;
-        if (tile < ntiles) acc[t] = mfma16(av, a.Sx[(long long)(k0 + lk) * Mx + tile * 16 + li], acc[t]);
-      }
-    }
+    gemm_right<T, TPW>(A, lda, a.Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[t][r] = (T)(acc[t][r] * a.g1_scale);
   }
-
-  // node of a sweep step in this subdomain (0-based subdomain s): first = s*k + 1 - delta
-  const int first = s * g.k + 1 - g.delta;
 
   // ---- GEMM1 epilogue stores -------------------------------------------------------------
   if (a.g1_in) {
@@ -117,9 +198,7 @@ k_rows(Geom g, RowArgs<T> a) {
     const bool owned = a.g1_step >= g.delta;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + t * nw;
-      if (tile >= ntiles) continue;
-      const int col = tile * 16 + li;
+      const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = rb * 16 + acc_row<T>(lk, r);
@@ -147,32 +226,19 @@ k_rows(Geom g, RowArgs<T> a) {
   // ---- form b (row-local) into LDS -------------------------------------------------------
   __syncthreads();  // every wave has finished reading A for GEMM1
   {
-    const int bnode = first + a.b_step;
     const T hT = (T)g.h;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + t * nw;
-      if (tile >= ntiles) continue;
-      const int col = tile * 16 + li;
+      const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rloc = acc_row<T>(lk, r), row = rb * 16 + rloc;
-        const bool in = row < g.my && col < g.mx;
+        const int rloc = acc_row<T>(lk, r);
         T b = 0;
         switch (a.b_mode) {
-          case B_RPRIME_PLUS_Y:
-            b = acc[t][r];
-            if (in && bnode >= 1) b += (T)a.rin[(long long)(bnode - 1) * g.nxy + row * g.mx + col];
-            break;
-          case B_H_YBUF_PLUS_Y:
-            b = hT * a.ybuf_in[s * a.ybuf_stride + (long long)row * Mx + col] + acc[t][r];
-            break;
-          case B_H_Y:
-            b = hT * acc[t][r];
-            break;
-          case B_INPUT:
-            if (in) b = (T)a.rin[(long long)s * g.nxy + row * g.mx + col];
-            break;
+          case B_RPRIME_PLUS_Y: b = pre[t][r] + acc[t][r]; break;
+          case B_H_YBUF_PLUS_Y: b = hT * pre[t][r] + acc[t][r]; break;
+          case B_H_Y: b = hT * acc[t][r]; break;
+          case B_INPUT: b = pre[t][r]; break;
         }
         A[rloc * lda + col] = b;
       }
@@ -183,20 +249,10 @@ k_rows(Geom g, RowArgs<T> a) {
   // ---- GEMM2: T = b S_x ------------------------------------------------------------------
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll 8
-  for (int k0 = 0; k0 < Mx; k0 += 4) {
-    const T av = A[li * lda + k0 + lk];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int tile = wave + t * nw;
-      if (tile < ntiles) acc[t] = mfma16(av, a.Sx[(long long)(k0 + lk) * Mx + tile * 16 + li], acc[t]);
-    }
-  }
+  gemm_right<T, TPW>(A, lda, a.Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
-    const int tile = wave + t * nw;
-    if (tile >= ntiles) continue;
-    const int col = tile * 16 + li;
+    const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = rb * 16 + acc_row<T>(lk, r);
@@ -220,7 +276,7 @@ struct ColArgs {
 };
 
 template <typename T, int TPW>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_cols(Geom g, ColArgs<T> a) {
   using acc_t = typename AccT<T>::type;
   extern __shared__ unsigned char smem_raw[];
@@ -231,7 +287,6 @@ k_cols(Geom g, ColArgs<T> a) {
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
-  const int ntiles = My >> 4;
 
   const T* src = a.in + s * a.in_stride + cb * 16;
   for (int e = threadIdx.x; e < My * 16; e += nthr) B[(e >> 4) * ldb + (e & 15)] = src[(long long)(e >> 4) * Mx + (e & 15)];
@@ -241,53 +296,49 @@ k_cols(Geom g, ColArgs<T> a) {
   for (int pass = 0; pass < 1 + a.two; ++pass) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-#pragma unroll 8
-    for (int k0 = 0; k0 < My; k0 += 4) {
-      const T bv = B[(k0 + lk) * ldb + li];
-#pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * nw;
-        if (tile < ntiles) acc[t] = mfma16(a.Sy[(long long)(k0 + lk) * My + tile * 16 + li], bv, acc[t]);
-      }
-    }
+    gemm_left<T, TPW>(a.Sy, B, ldb, My, wave, nw, li, lk, acc);
     if (pass == 0 && a.invlam) {
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * nw;
-        if (tile >= ntiles) continue;
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc[t][r] *= a.invlam[(long long)(tile * 16 + acc_row<T>(lk, r)) * Mx + cb * 16 + li];
-      }
+          acc[t][r] *= a.invlam[(long long)((wave + t * nw) * 16 + acc_row<T>(lk, r)) * Mx + cb * 16 + li];
     }
     if (pass == 0 && a.two) {
       __syncthreads();
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) {
-        const int tile = wave + t * nw;
-        if (tile >= ntiles) continue;
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) B[(tile * 16 + acc_row<T>(lk, r)) * ldb + li] = acc[t][r];
-      }
+        for (int r = 0; r < 4; ++r) B[((wave + t * nw) * 16 + acc_row<T>(lk, r)) * ldb + li] = acc[t][r];
       __syncthreads();
     }
   }
   T* dst = a.out + s * a.out_stride + cb * 16;
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int tile = wave + t * nw;
-    if (tile >= ntiles) continue;
+  for (int t = 0; t < TPW; ++t)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dst[(long long)(tile * 16 + acc_row<T>(lk, r)) * Mx + li] = acc[t][r];
-  }
+    for (int r = 0; r < 4; ++r)
+      dst[(long long)((wave + t * nw) * 16 + acc_row<T>(lk, r)) * Mx + li] = acc[t][r];
 }
 
 // ---- launch helpers ----------------------------------------------------------------------
+// Waves per workgroup for M/16 tiles: every wave gets the same number of tiles (<= 8).
+// The preferred width is 8 waves (KKTDD_GEMM_WAVES=4 selects 4).
+inline int wave_cap() {
+  static const int cap = [] {
+    const char* v = std::getenv("KKTDD_GEMM_WAVES");
+    return (v && std::atoi(v) == 4) ? 4 : 8;
+  }();
+  return cap;
+}
+
 inline int waves_for(int M) {
-  const int tiles = M / 16;
-  int nw = tiles < 4 ? tiles : 4;
-  while ((tiles + nw - 1) / nw > 8) nw *= 2;  // keep <= 8 tiles per wave
-  return nw;
+  const int t = M / 16, cap = wave_cap();
+  if (t <= 4) return t;
+  if (t <= 8) return (t == 8 && cap == 4) ? 4 : t;
+  if (t % cap == 0 && t / cap <= 8) return cap;
+  if (t % 4 == 0 && t / 4 <= 8) return 4;
+  return 8;   // padded extents make t a multiple of 8 here
 }
 
 // Dynamic LDS above 64 KiB has to be enabled per kernel before the first launch.
@@ -323,24 +374,29 @@ int cols_t(const Geom& g, const ColArgs<T>& a, int nslices, int nw, int kclass, 
   return 0;
 }
 
+#define KKT_TPW_DISPATCH(FN, TPWV, ...)                  \
+  switch (TPWV) {                                        \
+    case 1: return FN<T, 1>(__VA_ARGS__);                \
+    case 2: return FN<T, 2>(__VA_ARGS__);                \
+    case 3: return FN<T, 3>(__VA_ARGS__);                \
+    case 4: return FN<T, 4>(__VA_ARGS__);                \
+    case 5: return FN<T, 5>(__VA_ARGS__);                \
+    case 6: return FN<T, 6>(__VA_ARGS__);                \
+    case 7: return FN<T, 7>(__VA_ARGS__);                \
+    case 8: return FN<T, 8>(__VA_ARGS__);                \
+    default: return set_error(KKTDD_EINVAL, "unsupported tile count"); \
+  }
+
 template <typename T>
 int rows(const Geom& g, const RowArgs<T>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.Mx);
-  const int tpw = (g.Mx / 16 + nw - 1) / nw;
-  if (tpw <= 1) return rows_t<T, 1>(g, a, nslices, nw, kclass, s);
-  if (tpw <= 2) return rows_t<T, 2>(g, a, nslices, nw, kclass, s);
-  if (tpw <= 4) return rows_t<T, 4>(g, a, nslices, nw, kclass, s);
-  return rows_t<T, 8>(g, a, nslices, nw, kclass, s);
+  KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / nw, g, a, nslices, nw, kclass, s)
 }
 
 template <typename T>
 int cols(const Geom& g, const ColArgs<T>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.My);
-  const int tpw = (g.My / 16 + nw - 1) / nw;
-  if (tpw <= 1) return cols_t<T, 1>(g, a, nslices, nw, kclass, s);
-  if (tpw <= 2) return cols_t<T, 2>(g, a, nslices, nw, kclass, s);
-  if (tpw <= 4) return cols_t<T, 4>(g, a, nslices, nw, kclass, s);
-  return cols_t<T, 8>(g, a, nslices, nw, kclass, s);
+  KKT_TPW_DISPATCH(cols_t, g.My / 16 / nw, g, a, nslices, nw, kclass, s)
 }
 
 template <typename T>

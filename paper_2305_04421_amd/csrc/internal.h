@@ -34,7 +34,14 @@ struct Geom {
   __host__ __device__ long long padded() const { return (long long)Mx * My; }
 };
 
-inline int round_up16(int v) { return (v + 15) / 16 * 16; }
+// Padded sine-transform extent: a multiple of 16 whose tile count t = M/16 splits evenly over
+// the waves of a workgroup (t <= 8, or a multiple of 4 up to 32, or of 8 above).
+inline int pad_extent(int m) {
+  int t = (m + 15) / 16;
+  if (t > 8) t = (t + 3) / 4 * 4;
+  if (t > 32) t = (t + 7) / 8 * 8;
+  return 16 * t;
+}
 
 // Launch helpers report through this; the host driver converts to KKTDD_EHIP.
 #define KKT_HIP(call)                                       \

@@ -43,6 +43,8 @@ __device__ inline void block_sums(double (&acc)[MAXS], int count, double* out) {
   }
 }
 
+// Vectors are streamed as double2 (16-byte loads); V's leading dimension and the vector
+// pointers are 16-byte aligned, and an odd tail element is handled by thread 0 of block 0.
 template <int MAXV>
 __global__ void __launch_bounds__(kBlock)
 k_multidot(long long n, const double* __restrict__ V, long long ldv, int nv,
@@ -50,12 +52,25 @@ k_multidot(long long n, const double* __restrict__ V, long long ldv, int nv,
   double acc[MAXV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXV; ++i) acc[i] = 0.0;
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(w);
   const long long stride = (long long)gridDim.x * kBlock;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
-    const double wv = w[e];
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+    const double2 wv = w2[e];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i)
-      if (i < nv) acc[i] += V[i * ldv + e] * wv;
+      if (i < nv) {
+        const double2 v = V2[i * ld2 + e];
+        acc[i] += v.x * wv.x + v.y * wv.y;
+      }
+    acc[MAXV] += wv.x * wv.x + wv.y * wv.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double wv = w[n - 1];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < nv) acc[i] += V[i * ldv + n - 1] * wv;
     acc[MAXV] += wv * wv;
   }
   // compact: slot nv holds the norm
@@ -83,16 +98,36 @@ k_update_dot(long long n, const double* __restrict__ V, long long ldv, int nv,
   double acc[MAXV + 1];
 #pragma unroll
   for (int i = 0; i <= MAXV; ++i) acc[i] = 0.0;
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* w2 = reinterpret_cast<const double2*>(w);
+  double2* o2 = reinterpret_cast<double2*>(wout);
   const long long stride = (long long)gridDim.x * kBlock;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n; e += stride) {
-    double vv[MAXV];
-    double x = w[e];
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+    double2 vv[MAXV];
+    double2 x = w2[e];
 #pragma unroll
     for (int i = 0; i < MAXV; ++i) {
-      vv[i] = i < nv ? V[i * ldv + e] : 0.0;
+      vv[i] = i < nv ? V2[i * ld2 + e] : double2{0.0, 0.0};
+      x.x -= cf[i] * vv[i].x;
+      x.y -= cf[i] * vv[i].y;
+    }
+    o2[e] = x;
+    if (want_dots) {
+#pragma unroll
+      for (int i = 0; i < MAXV; ++i) acc[i] += vv[i].x * x.x + vv[i].y * x.y;
+    }
+    acc[MAXV] += x.x * x.x + x.y * x.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double vv[MAXV];
+    double x = w[n - 1];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i) {
+      vv[i] = i < nv ? V[i * ldv + n - 1] : 0.0;
       x -= cf[i] * vv[i];
     }
-    wout[e] = x;
+    wout[n - 1] = x;
     if (want_dots) {
 #pragma unroll
       for (int i = 0; i < MAXV; ++i) acc[i] += vv[i] * x;
@@ -220,6 +255,8 @@ int launch_multidot(long long n, const double* V, long long ldv, int nv, const d
     hipLaunchKernelGGL((k_multidot<8>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
   else if (nv <= 16)
     hipLaunchKernelGGL((k_multidot<16>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
+  else if (nv <= 24)
+    hipLaunchKernelGGL((k_multidot<24>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
   else if (nv <= 32)
     hipLaunchKernelGGL((k_multidot<32>), grid, block, 0, s, n, V, ldv, nv, w, want_norm, partials);
   else
@@ -239,6 +276,9 @@ int launch_update_dot(long long n, const double* V, long long ldv, int nv, const
                        want_dots, partials, gate);
   else if (nv <= 16)
     hipLaunchKernelGGL((k_update_dot<16>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
+                       want_dots, partials, gate);
+  else if (nv <= 24)
+    hipLaunchKernelGGL((k_update_dot<24>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
                        want_dots, partials, gate);
   else if (nv <= 32)
     hipLaunchKernelGGL((k_update_dot<32>), grid, block, 0, s, n, V, ldv, nv, vinv, coef, w, wout,
