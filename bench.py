@@ -11,8 +11,9 @@ FGMRES, matvec and coarse level) is timed the same way and reported beside it.
 
 Prints one JSON line.  Extra objects:
   roofline      the kernel class with the largest share of the float64 solve time, its
-                algorithmic bytes (or flops) over its HIP-event-timed launch durations,
-                against the MI355X peak; traffic from rocprofv3 counters when recorded
+                algorithmic bytes (or flops) over its launch durations, timed with HIP events
+                on one extra step whose solves run one after another, against the MI355X
+                peak; traffic from rocprofv3 counters when recorded
   cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample of the same
                 workload (the first FGMRES iterations), scaled to a whole solve
 """
@@ -30,9 +31,11 @@ METRIC = "KKT space-time unknowns solved/s to 1e-8 rel. residual, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 WORKLOADS = ("grid128", "grid128_w4")
-# HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel
-# calibration, for the kernel named in the roofline (None until measured for this build).
-TRAFFIC = None
+# HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE (FETCH_SIZE scaled by 2.0,
+# WRITE_SIZE by 1.0: what a 1 GiB device copy reads on those counters), per kernel class, as
+# recorded in profiles/arnoldi_grid128_fp64_hbm_counters.md for the current kernels.  A class
+# whose kernels changed since the counters were taken is absent (traffic null).
+TRAFFIC = {"arnoldi": 470.10e6, "matvec": 215.89e6}
 
 
 def parse():
@@ -47,6 +50,8 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-sweep path")
     ap.add_argument("--sequential", action="store_true",
                     help="solve the problems of a step one after another instead of as one batch")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB device-to-device once (a known-size kernel for HBM counters)")
     return ap.parse_args()
 
 
@@ -62,6 +67,12 @@ def main():
 
     torch.cuda.init()
     dev = torch.device("cuda:0")
+    if args.calibrate_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     probs = []
     for name in WORKLOADS:
         params, recipe = wl.config(name)
@@ -90,9 +101,6 @@ def main():
 
         for _ in range(warmup):
             step()
-        if profile:
-            for S in solvers:
-                S.profile(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(steps):
@@ -101,6 +109,14 @@ def main():
         dt = time.perf_counter() - t0
         prof = None
         if profile:
+            # Kernel timer: the same step once more, its solves one after another, with HIP
+            # events around every launch (concurrent solves would charge each kernel with
+            # the time it shares the GPU with the other problem's kernels).
+            for S in solvers:
+                S.profile(True)
+            for S, f, x in zip(solvers, fs, xs):
+                x.zero_()
+                S.solve(f, x=x, restart=args.restart, maxit=600, rtol=args.rtol)
             prof = {}
             for S in solvers:
                 for k, v in S.profile_read().items():
@@ -112,7 +128,7 @@ def main():
             S.close()
         return dt, stats, prof
 
-    # float64 path: timed region with the per-launch HIP-event timer on
+    # float64 path
     dt64, st64, prof64 = run_path("fp64", args.steps, args.warmup, profile=True)
     value64 = args.steps * sum(unknowns) / dt64
     result = {
@@ -142,12 +158,15 @@ def main():
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = TRAFFIC
+    roof["traffic"] = TRAFFIC.get(dom)
     roof["kernel_class"] = dom
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = 1e3 * d["ms"] / max(d["launches"], 1)
+    roof["algorithmic_bytes_per_launch"] = d["bytes"] / max(d["launches"], 1)
+    roof["algorithmic_flops_per_launch"] = d["flops"] / max(d["launches"], 1)
     roof["share_of_kernel_time"] = d["ms"] / total_ms if total_ms else None
-    roof["classes_ms_per_step"] = {k: v["ms"] / args.steps for k, v in prof64.items()}
+    roof["classes_ms_per_step"] = {k: v["ms"] for k, v in prof64.items()}
+    roof["timed_on"] = "one extra step, its solves run one after another, HIP events around every launch"
     result["roofline"] = roof
 
     if not args.no_mixed:
