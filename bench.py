@@ -16,6 +16,9 @@ Prints one JSON line.  Extra objects:
                 peak; traffic from rocprofv3 counters when recorded
   cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample of the same
                 workload (the first FGMRES iterations), scaled to a whole solve
+  hoisted       the same step with the transform-hoisted Schur block (sweeps as scalar
+                recurrences per sine mode between one forward and one inverse batched
+                transform), float64 and float32 transforms
 """
 
 import argparse
@@ -48,6 +51,7 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=4,
                     help="FGMRES iterations of the CPU oracle sample (0: skip the CPU baseline)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-sweep path")
+    ap.add_argument("--no-hoisted", action="store_true", help="skip the transform-hoisted (modal) paths")
     ap.add_argument("--sequential", action="store_true",
                     help="solve the problems of a step one after another instead of as one batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -80,8 +84,8 @@ def main():
         probs.append((name, params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
     unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
 
-    def run_path(precision, steps, warmup, profile):
-        solvers = [KKTSolver(p, precision) for _, p, _, _ in probs]
+    def run_path(precision, steps, warmup, profile, sweep="step"):
+        solvers = [KKTSolver(p, precision, sweep=sweep) for _, p, _, _ in probs]
         fs = [S.rhs(u0, ut) for S, (_, _, u0, ut) in zip(solvers, probs)]
         xs = [torch.zeros_like(f) for f in fs]
         stats = []
@@ -178,6 +182,18 @@ def main():
             "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st32)},
             "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st32)},
         }
+
+    if not args.no_hoisted:
+        # transform-hoisted Schur block (sine-mode sweeps), measured beside the per-step path
+        result["hoisted"] = {}
+        for prec in ("fp64", "fp32"):
+            dth, sth, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep="modal")
+            vh = args.steps * sum(unknowns) / dth
+            result["hoisted"][prec] = {
+                "value": vh, "ms_per_step": 1e3 * dth / args.steps, "ratio_vs_fp64_per_step": vh / value64,
+                "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, sth)},
+                "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, sth)},
+            }
 
     if args.cpu_iters > 0:
         result["cpu_baseline"] = cpu_baseline(args, probs[0][1], st64[0]["iters"])

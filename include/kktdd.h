@@ -56,6 +56,16 @@ enum kktdd_precision {
   KKTDD_FP32 = 1    /* float32 MFMA, float32 sweep state; float64 outer refinement          */
 };
 
+/* Placement of the spatial transforms in the fine-level sweeps.  Both compute the same
+ * two-level Schur block (Eqs. (13)-(15)) up to rounding. */
+enum kktdd_sweep {
+  KKTDD_SWEEP_STEP = 0,  /* every sweep step is a spatial solve: 4 sine-transform GEMMs per
+                            step, forward then adjoint, as the time integrator would do it     */
+  KKTDD_SWEEP_MODAL = 1  /* transforms hoisted out of the time loop: one batched forward
+                            transform of all slices, scalar recurrences per sine mode for the
+                            coarse solve, residual and both sweeps, one inverse transform      */
+};
+
 /* Problem of Eq. (1) discretised as in Sec. 2, and the time decomposition of Sec. 3. */
 typedef struct kktdd_problem {
   int32_t nx, ny;     /* grid intervals, >= 2                                              */
@@ -68,6 +78,7 @@ typedef struct kktdd_problem {
   int32_t overlap;    /* delta: nodes each subdomain extends to the left, 0..nt/n_sub      */
   int32_t coarse;     /* 0: one-level RASQ; 1: constant coarse basis; 2: constant+linear   */
   int32_t precision;  /* enum kktdd_precision                                              */
+  int32_t sweep;      /* enum kktdd_sweep                                                  */
 } kktdd_problem;
 
 typedef struct kktdd_stats {
@@ -86,7 +97,8 @@ typedef struct kktdd_handle kktdd_handle;
 /* Host-only check of a problem description; touches no device.  Rules: nx, ny >= 2;
  * nt >= 1; Lx, Ly, T, nu, omega positive and finite; n_sub >= 1 dividing nt;
  * 0 <= overlap <= nt/n_sub; coarse in {0,1,2}; coarse == 2 needs nt/n_sub >= 2 (the linear
- * basis function of Eq. (14) is constant on a one-step subdomain); precision known.
+ * basis function of Eq. (14) is constant on a one-step subdomain); nx, ny <= 1024;
+ * precision and sweep known.
  * Returns KKTDD_OK or KKTDD_EINVAL. */
 int kkt_validate(const kktdd_problem* prob);
 

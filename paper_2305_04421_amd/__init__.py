@@ -23,15 +23,15 @@ def library_path():
     return _lib.LIB_PATH
 
 
-def validate(params, precision="fp64"):
+def validate(params, precision="fp64", sweep="step"):
     """Host-only parameter check (no device); raises KKTDDError on a bad problem."""
-    prob = _lib.make_problem(params, precision)
+    prob = _lib.make_problem(params, precision, sweep)
     _lib.check(_lib.load().kkt_validate(ctypes.byref(prob)), "kkt_validate")
 
 
-def memory_plan(params, precision="fp64", restart=0):
+def memory_plan(params, precision="fp64", restart=0, sweep="step"):
     """Device bytes a handle (plus a Krylov basis of `restart` vectors) needs; host-only."""
-    prob = _lib.make_problem(params, precision)
+    prob = _lib.make_problem(params, precision, sweep)
     out = ctypes.c_size_t(0)
     _lib.check(_lib.load().kkt_memory_plan(ctypes.byref(prob), int(restart), ctypes.byref(out)),
                "kkt_memory_plan")
@@ -50,15 +50,20 @@ def _ptr(t, numel, name):
 
 
 class KKTSolver:
-    """One problem handle on the current device and torch's current stream."""
+    """One problem handle on the current device and torch's current stream.
 
-    def __init__(self, params, precision="fp64", stream=None):
+    precision: "fp64" or "fp32" (sweeps and their sine-transform GEMMs);
+    sweep: "step" (a spatial solve at every sweep step) or "modal" (transforms hoisted).
+    """
+
+    def __init__(self, params, precision="fp64", stream=None, sweep="step"):
         import torch
         lib = _lib.load()
         self.params = dict(params)
         self.precision = precision
+        self.sweep = sweep
         self._stream = stream if stream is not None else torch.cuda.current_stream()
-        prob = _lib.make_problem(params, precision)
+        prob = _lib.make_problem(params, precision, sweep)
         handle = ctypes.c_void_p()
         _lib.check(lib.kkt_create(ctypes.byref(prob), ctypes.c_void_p(self._stream.cuda_stream),
                                   ctypes.byref(handle)), "kkt_create")

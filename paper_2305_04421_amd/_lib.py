@@ -16,6 +16,9 @@ OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 # enum kktdd_precision
 FP64, FP32 = 0, 1
 PRECISIONS = {"fp64": FP64, "fp32": FP32}
+# enum kktdd_sweep
+SWEEP_STEP, SWEEP_MODAL = 0, 1
+SWEEPS = {"step": SWEEP_STEP, "modal": SWEEP_MODAL}
 
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_rhs",
             "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
@@ -31,7 +34,7 @@ class Problem(ctypes.Structure):
                 ("nt", ctypes.c_int32), ("T", ctypes.c_double),
                 ("nu", ctypes.c_double), ("omega", ctypes.c_double),
                 ("n_sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
-                ("coarse", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("coarse", ctypes.c_int32), ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -86,13 +89,15 @@ def load():
     return lib
 
 
-def make_problem(params, precision="fp64"):
+def make_problem(params, precision="fp64", sweep="step"):
     """Problem struct from a parameter dict (keys nx, ny, nt, Lx, Ly, T, nu, omega, n_sub, overlap, coarse)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    swp = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
     return Problem(int(params["nx"]), int(params["ny"]), float(params.get("Lx", 1.0)),
                    float(params.get("Ly", 1.0)), int(params["nt"]), float(params.get("T", 1.0)),
                    float(params.get("nu", 1.0)), float(params.get("omega", 1e-2)),
                    int(params.get("n_sub", 1)), int(params.get("overlap", 1)),
-                   int(params.get("coarse", 2)), PRECISIONS[precision] if isinstance(precision, str) else int(precision))
+                   int(params.get("coarse", 2)), prec, swp)
 
 
 class KKTDDError(RuntimeError):

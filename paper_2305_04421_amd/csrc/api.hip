@@ -99,9 +99,12 @@ struct kktdd_handle {
   double *Sx64 = nullptr, *Sy64 = nullptr, *invlam64 = nullptr;
   float *Sx32 = nullptr, *Sy32 = nullptr, *invlam32 = nullptr;
   double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
-  // sweeps
+  // per-step sweeps
   void *Tbuf = nullptr, *Ubuf = nullptr, *Ybuf = nullptr;
   double* rprime = nullptr;
+  // modal (transform-hoisted) sweeps
+  void *Rhat = nullptr, *Mtmp = nullptr;
+  double* Ysc = nullptr;
   // coarse
   double *r0 = nullptr, *c0 = nullptr, *Dc0 = nullptr, *DDc0 = nullptr;
   double *chat = nullptr, *ctmp = nullptr, *cfac = nullptr;
@@ -164,6 +167,7 @@ int validate(const kktdd_problem* p) {
   if (p->coarse < 0 || p->coarse > 2) return bad("coarse must be 0, 1 or 2");
   if (p->coarse == 2 && k < 2) return bad("a linear coarse basis needs nt/n_sub >= 2");
   if (p->precision != KKTDD_FP64 && p->precision != KKTDD_FP32) return bad("unknown precision");
+  if (p->sweep != KKTDD_SWEEP_STEP && p->sweep != KKTDD_SWEEP_MODAL) return bad("unknown sweep placement");
   if ((long long)p->nt * (p->nx - 1) * (p->ny - 1) > (1LL << 40)) return bad("problem too large");
   return KKTDD_OK;
 }
@@ -202,16 +206,23 @@ struct Plan {
   size_t total() const { return tables + sweeps + coarse + krylov; }
 };
 
-Plan plan(const Geom& g, int precision, int R) {
+constexpr int kModalRegSteps = 32;   // must match the register sweep length in modal.hip
+
+Plan plan(const Geom& g, int precision, int sweep, int R) {
   const size_t el = precision == KKTDD_FP32 ? 4 : 8;
   const size_t MM = (size_t)g.padded();
   Plan p{};
   p.tables = ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My + MM) * 12 + (size_t)(g.mx + g.my) * 8;
-  p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el + (size_t)g.P * 8;
+  if (sweep == KKTDD_SWEEP_MODAL) {
+    p.sweeps = 2 * (size_t)g.nt * MM * el;
+    if (g.L > kModalRegSteps) p.sweeps += (size_t)g.nd * g.L * MM * 8;
+  } else {
+    p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el + (size_t)g.P * 8;
+  }
   if (g.nb > 0) {
     const int hb = 2 * g.nb - 1;
-    p.coarse = (size_t)g.nc * g.nxy * 8 * 4 + (size_t)g.nc * MM * 8 * 2 +
-               (size_t)g.nxy * g.nc * (hb + 1) * 8;
+    p.coarse = (size_t)g.nc * MM * 8 * 2 + (size_t)g.nxy * g.nc * (hb + 1) * 8;
+    if (sweep == KKTDD_SWEEP_STEP) p.coarse += (size_t)g.nc * g.nxy * 8 * 4;
   }
   p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
   if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
@@ -327,7 +338,25 @@ int build_coarse(kktdd_handle* H) {
   return 0;
 }
 
+// Transform-hoisted Schur block (sine-mode space): see modal.hip.
+int schur_apply_modal(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
+  const Geom& g = H->g;
+  hipStream_t s = H->stream;
+  const int prec = H->prob.precision;
+  if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), rw, dscale, H->Mtmp, H->Rhat, g.nt, s)) return e;
+  const double* c0 = nullptr;
+  if (g.nb > 0) {
+    if (int e = launch_modal_restrict(g, prec, H->Rhat, H->chat, s)) return e;
+    if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
+    c0 = H->chat;
+  }
+  if (int e = launch_modal_sweeps(g, prec, H->Rhat, c0, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
+  const double norm = 4.0 / ((double)H->prob.nx * H->prob.ny);
+  return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, s);
+}
+
 int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
+  if (H->prob.sweep == KKTDD_SWEEP_MODAL) return schur_apply_modal(H, rw, dscale, zw);
   const Geom& g = H->g;
   hipStream_t s = H->stream;
   const double* c0 = nullptr;
@@ -397,7 +426,7 @@ int kkt_validate(const kktdd_problem* prob) { return validate(prob); }
 int kkt_memory_plan(const kktdd_problem* prob, int32_t restart, size_t* bytes) {
   if (int e = validate(prob)) return e;
   if (!bytes || restart < 0) return set_error(KKTDD_EINVAL, "bad memory-plan arguments");
-  *bytes = plan(make_geom(*prob), prob->precision, restart).total();
+  *bytes = plan(make_geom(*prob), prob->precision, prob->sweep, restart).total();
   return KKTDD_OK;
 }
 
@@ -427,7 +456,7 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
     return set_error(KKTDD_EHIP, "hipMemGetInfo failed");
   }
   const Geom& g = H->g;
-  const Plan pl = plan(g, prob->precision, 0);
+  const Plan pl = plan(g, prob->precision, prob->sweep, 0);
   if (pl.total() > free_b) {
     delete H;
     char buf[160];
@@ -437,7 +466,15 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
   if (int e = build_tables(H)) return fail(e);
   const size_t MM = (size_t)g.padded();
   const size_t el = H->elem;
-  {
+  if (prob->sweep == KKTDD_SWEEP_MODAL) {
+    unsigned char *rh, *mt;
+    if (int e = dalloc(H, &rh, (size_t)g.nt * MM * el)) return fail(e);
+    if (int e = dalloc(H, &mt, (size_t)g.nt * MM * el)) return fail(e);
+    H->Rhat = rh;
+    H->Mtmp = mt;
+    if (g.L > kModalRegSteps)
+      if (int e = dalloc(H, &H->Ysc, (size_t)g.nd * g.L * MM)) return fail(e);
+  } else {
     unsigned char *t, *u, *y;
     if (int e = dalloc(H, &t, (size_t)g.nd * MM * el)) return fail(e);
     if (int e = dalloc(H, &u, (size_t)g.nd * MM * el)) return fail(e);
@@ -445,13 +482,15 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
     H->Tbuf = t;
     H->Ubuf = u;
     H->Ybuf = y;
+    if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
   }
-  if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
   if (g.nb > 0) {
-    if (int e = dalloc(H, &H->r0, (size_t)g.nc * g.nxy)) return fail(e);
-    if (int e = dalloc(H, &H->c0, (size_t)g.nc * g.nxy)) return fail(e);
-    if (int e = dalloc(H, &H->Dc0, (size_t)g.nc * g.nxy)) return fail(e);
-    if (int e = dalloc(H, &H->DDc0, (size_t)g.nc * g.nxy)) return fail(e);
+    if (prob->sweep == KKTDD_SWEEP_STEP) {
+      if (int e = dalloc(H, &H->r0, (size_t)g.nc * g.nxy)) return fail(e);
+      if (int e = dalloc(H, &H->c0, (size_t)g.nc * g.nxy)) return fail(e);
+      if (int e = dalloc(H, &H->Dc0, (size_t)g.nc * g.nxy)) return fail(e);
+      if (int e = dalloc(H, &H->DDc0, (size_t)g.nc * g.nxy)) return fail(e);
+    }
     if (int e = dalloc(H, &H->chat, (size_t)g.nc * MM)) return fail(e);
     if (int e = dalloc(H, &H->ctmp, (size_t)g.nc * MM)) return fail(e);
     // padded sine-mode slices must start (and stay) zero outside the mode grid

@@ -132,6 +132,7 @@ struct RowArgs {
   int b_mode;
   int b_step;                // sweep step whose right-hand side is formed (B_RPRIME_PLUS_Y)
   const double* rin;         // r' field (nt slices) or plain input slices (B_INPUT)
+  const double* in_scale;    // device factor of the B_INPUT slices (nullptr: 1)
   const T* ybuf_in;          // padded (B_H_YBUF_PLUS_Y)
   long long ybuf_stride;
   T* g2_out;                 // padded
@@ -160,6 +161,7 @@ k_rows(Geom g, RowArgs<T> a) {
   T pre[TPW][4];
   if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
     const int bnode = first + a.b_step;
+    const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
 #pragma unroll
     for (int t = 0; t < TPW; ++t) {
       const int col = (wave + t * nw) * 16 + li;
@@ -173,7 +175,7 @@ k_rows(Geom g, RowArgs<T> a) {
         } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
           v = a.ybuf_in[s * a.ybuf_stride + (long long)row * Mx + col];
         } else if (in) {
-          v = (T)a.rin[(long long)s * g.nxy + row * g.mx + col];
+          v = (T)(isc * a.rin[(long long)s * g.nxy + row * g.mx + col]);
         }
         pre[t][r] = v;
       }
@@ -501,7 +503,53 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
   return rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s);
 }
 
+template <typename T>
+int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* in,
+                  const double* dscale, void* tmp, void* out, int nslices, hipStream_t s) {
+  const long long MM = g.padded();
+  RowArgs<T> r = row_args<T>(Sx);
+  r.b_mode = B_INPUT;
+  r.rin = in;
+  r.in_scale = dscale;
+  r.g2_out = static_cast<T*>(tmp);
+  r.g2_stride = MM;
+  if (int e = rows<T>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s)) return e;
+  ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(tmp), MM, nullptr, 0,
+               static_cast<T*>(out), MM};
+  return cols<T>(g, c, nslices, KKTDD_K_SWEEP_COLS, s);
+}
+
+template <typename T>
+int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in, void* tmp,
+                  double* out, int nslices, double norm, hipStream_t s) {
+  const long long MM = g.padded();
+  ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(in), MM, nullptr, 0,
+               static_cast<T*>(tmp), MM};
+  if (int e = cols<T>(g, c, nslices, KKTDD_K_SWEEP_COLS, s)) return e;
+  RowArgs<T> r = row_args<T>(Sx);
+  r.g1_in = static_cast<const T*>(tmp);
+  r.g1_stride = MM;
+  r.g1_scale = norm;
+  r.out_mode = OUT_PLAIN;
+  r.out64 = out;
+  return rows<T>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s);
+}
+
 }  // namespace
+
+int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
+                       const double* in, const double* dscale, void* tmp, void* out, int nslices,
+                       hipStream_t s) {
+  if (precision == KKTDD_FP32) return dst_forward_t<float>(g, Sx, Sy, in, dscale, tmp, out, nslices, s);
+  return dst_forward_t<double>(g, Sx, Sy, in, dscale, tmp, out, nslices, s);
+}
+
+int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
+                       const void* in, void* tmp, double* out, int nslices, double norm,
+                       hipStream_t s) {
+  if (precision == KKTDD_FP32) return dst_inverse_t<float>(g, Sx, Sy, in, tmp, out, nslices, norm, s);
+  return dst_inverse_t<double>(g, Sx, Sy, in, tmp, out, nslices, norm, s);
+}
 
 int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const void* Sy,
                          const void* invlam, const double* b, double* x, int nslices,

@@ -90,6 +90,23 @@ int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const d
 int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
                        double* c0, double* tmp, double norm, hipStream_t s);
 
+// Batched 2-D sine transforms of nslices slices in the handle's precision:
+//   forward  out = S_y (scale*in) S_x   (in: unpadded float64 slices; out, tmp: padded)
+//   inverse  out = norm * S_y in S_x    (in, tmp: padded; out: unpadded float64 slices)
+int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
+                       const double* in, const double* dscale, void* tmp, void* out, int nslices,
+                       hipStream_t s);
+int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
+                       const void* in, void* tmp, double* out, int nslices, double norm,
+                       hipStream_t s);
+
+// ---- modal.hip: transform-hoisted Schur block (sine-mode space) --------------------------
+int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
+                          hipStream_t s);
+int launch_modal_sweeps(const Geom& g, int precision, const void* rhat, const double* c0,
+                        const double* lamx, const double* lamy, double* yscratch, void* zhat,
+                        hipStream_t s);
+
 // ---- coarse.hip: Nicolaides coarse level --------------------------------------------------
 int launch_restrict(const Geom& g, const double* rw, const double* dscale, double* r0,
                     hipStream_t s);

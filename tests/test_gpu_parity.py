@@ -41,12 +41,14 @@ CASES = {
     "full_tiles_overlap_k": wl.problem(nx=129, ny=65, nt=16, Lx=1.0, Ly=0.5, nu=0.2, omega=1e-4, n_sub=4, overlap=4,
                                        coarse=1),
     "tiny32": wl.config("tiny32")[0],
+    "long_subdomains": wl.problem(nx=10, ny=12, nt=80, Lx=1.0, Ly=2.0, nu=1.0, omega=1e-2, n_sub=2, overlap=1,
+                                  coarse=2),
 }
 
 
-def solver(params, precision="fp64"):
+def solver(params, precision="fp64", sweep="step"):
     from paper_2305_04421_amd import KKTSolver
-    return KKTSolver(params, precision)
+    return KKTSolver(params, precision, sweep=sweep)
 
 
 @pytest.mark.parametrize("name", list(CASES))
@@ -93,23 +95,35 @@ def test_spatial_solve_tile_shapes(nx, ny, precision, tol):
     assert relerr(x, sp.solve_diag_block(p, b, 1.3)) <= tol
 
 
+@pytest.mark.parametrize("sweep", ["step", "modal"])
 @pytest.mark.parametrize("coarse", [0, 1, 2])
-@pytest.mark.parametrize("name", ["tiny_ragged", "ragged_tiles", "full_tiles_overlap_k", "tiny32"])
-def test_precond_matches_oracle(name, coarse):
+@pytest.mark.parametrize("name", ["tiny_ragged", "ragged_tiles", "full_tiles_overlap_k", "tiny32", "long_subdomains"])
+def test_precond_matches_oracle(name, coarse, sweep):
     params = dict(CASES[name], coarse=coarse)
     p = Problem(**params).validate()
     r = wl.random_field((3,) + p.field_shape, 103)
-    with solver(params) as S:
+    with solver(params, sweep=sweep) as S:
         z = host(S.precond(dev(r)), r.shape)
     want = pc.apply_Pinv(p, r)
     assert relerr(z, want) <= 1e-11
 
 
-def test_precond_degenerate_one_level():
+@pytest.mark.parametrize("sweep", ["step", "modal"])
+def test_precond_fp32_close_to_oracle(sweep):
+    params = CASES["tiny32"]
+    p = Problem(**params).validate()
+    r = wl.random_field((3,) + p.field_shape, 107)
+    with solver(params, "fp32", sweep=sweep) as S:
+        z = host(S.precond(dev(r)), r.shape)
+    assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-4
+
+
+@pytest.mark.parametrize("sweep", ["step", "modal"])
+def test_precond_degenerate_one_level(sweep):
     params = CASES["degenerate"]
     p = Problem(**params).validate()
     r = wl.random_field((3,) + p.field_shape, 104)
-    with solver(params) as S:
+    with solver(params, sweep=sweep) as S:
         z = host(S.precond(dev(r)), r.shape)
     assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-12
 
@@ -129,14 +143,15 @@ def _oracle_solve(p, f, restart, maxit, rtol):
                     restart=restart, maxit=maxit, rtol=rtol)
 
 
+@pytest.mark.parametrize("sweep", ["step", "modal"])
 @pytest.mark.parametrize("name", ["ragged_tiles", "tiny32"])
-def test_fgmres_matches_oracle_at_fixed_iterations(name):
+def test_fgmres_matches_oracle_at_fixed_iterations(name, sweep):
     params = CASES[name]
     p = Problem(**params).validate()
     u0, ut = wl.sine_mode_data(params, 7, 8)
     f = op.rhs(p, u0, ut)
     ref = _oracle_solve(p, f, restart=4, maxit=7, rtol=1e-15)
-    with solver(params) as S:
+    with solver(params, sweep=sweep) as S:
         x, st = S.solve(dev(f), restart=4, maxit=7, rtol=1e-15)
     assert st["iters"] == ref.iterations == 7
     assert st["status"] == 1
@@ -144,13 +159,14 @@ def test_fgmres_matches_oracle_at_fixed_iterations(name):
     assert np.linalg.norm(xs - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
 
 
-def test_fgmres_converges_like_oracle_tiny32():
+@pytest.mark.parametrize("sweep", ["step", "modal"])
+def test_fgmres_converges_like_oracle_tiny32(sweep):
     params, recipe = wl.config("tiny32")
     p = Problem(**params).validate()
     u0, ut = wl.data(params, recipe)
     f = op.rhs(p, u0, ut)
     ref = _oracle_solve(p, f, restart=30, maxit=300, rtol=1e-8)
-    with solver(params) as S:
+    with solver(params, sweep=sweep) as S:
         fd = S.rhs(dev(u0), dev(ut))
         x, st = S.solve(fd, restart=30, maxit=300, rtol=1e-8)
     assert st["status"] == 0 and ref.converged
@@ -162,12 +178,13 @@ def test_fgmres_converges_like_oracle_tiny32():
     assert np.linalg.norm(f - op.apply_K(p, xs)) <= 1e-8 * np.linalg.norm(f)
 
 
-def test_fp32_sweeps_reach_same_tolerance_within_two_iterations():
+@pytest.mark.parametrize("sweep", ["step", "modal"])
+def test_fp32_sweeps_reach_same_tolerance_within_two_iterations(sweep):
     params, recipe = wl.config("tiny32")
     p = Problem(**params).validate()
     u0, ut = wl.data(params, recipe)
     f = op.rhs(p, u0, ut)
-    with solver(params, "fp64") as S64, solver(params, "fp32") as S32:
+    with solver(params, "fp64", sweep=sweep) as S64, solver(params, "fp32", sweep=sweep) as S32:
         fd = dev(f)
         x64, st64 = S64.solve(fd, restart=30, maxit=300, rtol=1e-8)
         x32, st32 = S32.solve(fd, restart=30, maxit=300, rtol=1e-8)
