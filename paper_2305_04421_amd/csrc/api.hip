@@ -208,6 +208,17 @@ struct Plan {
 
 constexpr int kModalRegSteps = 32;   // must match the register sweep length in modal.hip
 
+// Which buffers a configuration needs.  The coarse level runs in physical space (its own
+// float64 transforms of 2N_D slices, r' formed pointwise in float64) for the per-step sweeps
+// and for the float32 modal sweeps: float32 transforms of r itself would round r before the
+// cancellation in r - S_hat c.  Float64 modal sweeps do the coarse level in mode space.
+bool physical_coarse(const Geom& g, int precision, int sweep) {
+  return g.nb > 0 && (sweep == KKTDD_SWEEP_STEP || precision == KKTDD_FP32);
+}
+bool needs_rprime(const Geom& g, int precision, int sweep) {
+  return sweep == KKTDD_SWEEP_STEP || physical_coarse(g, precision, sweep);
+}
+
 Plan plan(const Geom& g, int precision, int sweep, int R) {
   const size_t el = precision == KKTDD_FP32 ? 4 : 8;
   const size_t MM = (size_t)g.padded();
@@ -217,12 +228,13 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
     p.sweeps = 2 * (size_t)g.nt * MM * el;
     if (g.L > kModalRegSteps) p.sweeps += (size_t)g.nd * g.L * MM * 8;
   } else {
-    p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el + (size_t)g.P * 8;
+    p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el;
   }
+  if (needs_rprime(g, precision, sweep)) p.sweeps += (size_t)g.P * 8;
   if (g.nb > 0) {
     const int hb = 2 * g.nb - 1;
     p.coarse = (size_t)g.nc * MM * 8 * 2 + (size_t)g.nxy * g.nc * (hb + 1) * 8;
-    if (sweep == KKTDD_SWEEP_STEP) p.coarse += (size_t)g.nc * g.nxy * 8 * 4;
+    if (physical_coarse(g, precision, sweep)) p.coarse += (size_t)g.nc * g.nxy * 8 * 4;
   }
   p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
   if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
@@ -338,25 +350,9 @@ int build_coarse(kktdd_handle* H) {
   return 0;
 }
 
-// Transform-hoisted Schur block (sine-mode space): see modal.hip.
-int schur_apply_modal(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
-  const Geom& g = H->g;
-  hipStream_t s = H->stream;
-  const int prec = H->prob.precision;
-  if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), rw, dscale, H->Mtmp, H->Rhat, g.nt, s)) return e;
-  const double* c0 = nullptr;
-  if (g.nb > 0) {
-    if (int e = launch_modal_restrict(g, prec, H->Rhat, H->chat, s)) return e;
-    if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
-    c0 = H->chat;
-  }
-  if (int e = launch_modal_sweeps(g, prec, H->Rhat, c0, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
-  const double norm = 4.0 / ((double)H->prob.nx * H->prob.ny);
-  return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, s);
-}
-
-int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
-  if (H->prob.sweep == KKTDD_SWEEP_MODAL) return schur_apply_modal(H, rw, dscale, zw);
+// Coarse correction in physical space (float64): c0 = S_hat_0^{-1} Z^T r, then
+// r' = scale*r - S_hat Z c0 pointwise.  Returns c0 (nullptr without a coarse level).
+int coarse_physical(kktdd_handle* H, const double* rw, const double* dscale, const double** c0out) {
   const Geom& g = H->g;
   hipStream_t s = H->stream;
   const double* c0 = nullptr;
@@ -370,7 +366,41 @@ int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double*
     if (int e = launch_apply_D(g, H->Dc0, H->DDc0, g.nc, g.sigma, s)) return e;
     c0 = H->c0;
   }
-  if (int e = launch_residual_prime(g, rw, dscale, c0, H->Dc0, H->DDc0, H->rprime, s)) return e;
+  *c0out = c0;
+  return launch_residual_prime(g, rw, dscale, c0, H->Dc0, H->DDc0, H->rprime, s);
+}
+
+// Transform-hoisted Schur block (sine-mode space): see modal.hip.
+int schur_apply_modal(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
+  const Geom& g = H->g;
+  hipStream_t s = H->stream;
+  const int prec = H->prob.precision;
+  const double norm = 4.0 / ((double)H->prob.nx * H->prob.ny);
+  if (physical_coarse(g, prec, KKTDD_SWEEP_MODAL)) {
+    // float32 transforms: coarse level and r' in float64 physical space, sweeps in mode space
+    const double* c0 = nullptr;
+    if (int e = coarse_physical(H, rw, dscale, &c0)) return e;
+    if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), H->rprime, nullptr, H->Mtmp, H->Rhat, g.nt, s)) return e;
+    if (int e = launch_modal_sweeps(g, prec, H->Rhat, nullptr, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
+    return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, c0, s);
+  }
+  if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), rw, dscale, H->Mtmp, H->Rhat, g.nt, s)) return e;
+  const double* c0 = nullptr;
+  if (g.nb > 0) {
+    if (int e = launch_modal_restrict(g, prec, H->Rhat, H->chat, s)) return e;
+    if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
+    c0 = H->chat;
+  }
+  if (int e = launch_modal_sweeps(g, prec, H->Rhat, c0, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
+  return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, nullptr, s);
+}
+
+int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double* zw) {
+  if (H->prob.sweep == KKTDD_SWEEP_MODAL) return schur_apply_modal(H, rw, dscale, zw);
+  const Geom& g = H->g;
+  hipStream_t s = H->stream;
+  const double* c0 = nullptr;
+  if (int e = coarse_physical(H, rw, dscale, &c0)) return e;
   return launch_sweeps(g, H->prob.precision, H->Sx(), H->Sy(), H->invlam(), H->rprime, c0, zw,
                        H->Tbuf, H->Ubuf, H->Ybuf, s);
 }
@@ -482,10 +512,11 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
     H->Tbuf = t;
     H->Ubuf = u;
     H->Ybuf = y;
-    if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
   }
+  if (needs_rprime(g, prob->precision, prob->sweep))
+    if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
   if (g.nb > 0) {
-    if (prob->sweep == KKTDD_SWEEP_STEP) {
+    if (physical_coarse(g, prob->precision, prob->sweep)) {
       if (int e = dalloc(H, &H->r0, (size_t)g.nc * g.nxy)) return fail(e);
       if (int e = dalloc(H, &H->c0, (size_t)g.nc * g.nxy)) return fail(e);
       if (int e = dalloc(H, &H->Dc0, (size_t)g.nc * g.nxy)) return fail(e);

@@ -127,7 +127,7 @@ struct RowArgs {
   long long ystore_stride;
   int out_mode;
   double* out64;             // OUT_OWNED: z_w field (nt slices); OUT_PLAIN: nslices slices
-  const double* c0;          // coarse slots for OUT_OWNED (nullptr: none)
+  const double* c0;          // coarse slots added to OUT_OWNED / OUT_PLAIN field output (nullptr: none)
   int g1_step;               // sweep step of the GEMM1 result (OUT_OWNED)
   int b_mode;
   int b_step;                // sweep step whose right-hand side is formed (B_RPRIME_PLUS_Y)
@@ -208,7 +208,14 @@ k_rows(Geom g, RowArgs<T> a) {
         if (a.ystore) a.ystore[s * a.ystore_stride + (long long)row * Mx + col] = v;
         if (row < g.my && col < g.mx) {
           if (a.out_mode == OUT_PLAIN) {
-            a.out64[(long long)s * g.nxy + row * g.mx + col] = (double)v;
+            double val = (double)v;
+            if (a.c0) {   // slice s is time-node s+1 of a field: add the prolonged coarse part
+              const int n = s + 1, sd = s / g.k;
+              const double* c = a.c0 + (long long)(g.nb * sd) * g.nxy + row * g.mx + col;
+              val += c[0];
+              if (g.nb == 2) val += (-1.0 + 2.0 * (double)(n - sd * g.k) / g.k) * c[g.nxy];
+            }
+            a.out64[(long long)s * g.nxy + row * g.mx + col] = val;
           } else if (a.out_mode == OUT_OWNED && owned) {
             const long long pt = row * g.mx + col;
             double val = (double)v;
@@ -521,7 +528,7 @@ int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* i
 
 template <typename T>
 int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in, void* tmp,
-                  double* out, int nslices, double norm, hipStream_t s) {
+                  double* out, int nslices, double norm, const double* c0, hipStream_t s) {
   const long long MM = g.padded();
   ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(in), MM, nullptr, 0,
                static_cast<T*>(tmp), MM};
@@ -532,6 +539,7 @@ int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in,
   r.g1_scale = norm;
   r.out_mode = OUT_PLAIN;
   r.out64 = out;
+  r.c0 = c0;
   return rows<T>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s);
 }
 
@@ -546,9 +554,9 @@ int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void*
 
 int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const void* in, void* tmp, double* out, int nslices, double norm,
-                       hipStream_t s) {
-  if (precision == KKTDD_FP32) return dst_inverse_t<float>(g, Sx, Sy, in, tmp, out, nslices, norm, s);
-  return dst_inverse_t<double>(g, Sx, Sy, in, tmp, out, nslices, norm, s);
+                       const double* c0, hipStream_t s) {
+  if (precision == KKTDD_FP32) return dst_inverse_t<float>(g, Sx, Sy, in, tmp, out, nslices, norm, c0, s);
+  return dst_inverse_t<double>(g, Sx, Sy, in, tmp, out, nslices, norm, c0, s);
 }
 
 int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const void* Sy,

@@ -92,13 +92,14 @@ int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const 
 
 // Batched 2-D sine transforms of nslices slices in the handle's precision:
 //   forward  out = S_y (scale*in) S_x   (in: unpadded float64 slices; out, tmp: padded)
-//   inverse  out = norm * S_y in S_x    (in, tmp: padded; out: unpadded float64 slices)
+//   inverse  out = norm * S_y in S_x    (in, tmp: padded; out: unpadded float64 slices),
+//            plus the coarse part Z c0 when c0 != nullptr (the slices are time-nodes 1..nt)
 int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const double* in, const double* dscale, void* tmp, void* out, int nslices,
                        hipStream_t s);
 int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const void* in, void* tmp, double* out, int nslices, double norm,
-                       hipStream_t s);
+                       const double* c0, hipStream_t s);
 
 // ---- modal.hip: transform-hoisted Schur block (sine-mode space) --------------------------
 int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
