@@ -53,7 +53,10 @@ enum kktdd_status {
  * Krylov vectors, the coarse level and every reduction stay float64. */
 enum kktdd_precision {
   KKTDD_FP64 = 0,   /* float64 MFMA                                                        */
-  KKTDD_FP32 = 1    /* float32 MFMA, float32 sweep state; float64 outer refinement          */
+  KKTDD_FP32 = 1,   /* float32 MFMA, float32 sweep state; float64 outer refinement          */
+  KKTDD_BF16 = 2,   /* bfloat16 MFMA, float32 accumulation and sweep state                  */
+  KKTDD_BF16X3 = 3, /* each float32 operand split into 2 bfloat16 parts, 3 part products    */
+  KKTDD_BF16X6 = 4  /* each float32 operand split into 3 bfloat16 parts, 6 part products    */
 };
 
 /* Placement of the spatial transforms in the fine-level sweeps.  Both compute the same

@@ -14,8 +14,8 @@ LIB_PATH = os.path.join(HERE, "libkktdd.so")
 # enum kktdd_status
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 # enum kktdd_precision
-FP64, FP32 = 0, 1
-PRECISIONS = {"fp64": FP64, "fp32": FP32}
+FP64, FP32, BF16, BF16X3, BF16X6 = 0, 1, 2, 3, 4
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3, "bf16x6": BF16X6}
 # enum kktdd_sweep
 SWEEP_STEP, SWEEP_MODAL = 0, 1
 SWEEPS = {"step": SWEEP_STEP, "modal": SWEEP_MODAL}

@@ -118,10 +118,25 @@ struct kktdd_handle {
   double* host_hcol = nullptr;                 // pinned
   Prof prof;
 
-  const void* Sx() const { return prob.precision == KKTDD_FP32 ? (const void*)Sx32 : (const void*)Sx64; }
-  const void* Sy() const { return prob.precision == KKTDD_FP32 ? (const void*)Sy32 : (const void*)Sy64; }
+  uint16_t *SxBF = nullptr, *SyBF = nullptr;  // bfloat16 parts (3 per matrix) of S_x, S_y
+
+  // sine-matrix operand and eigenvalue table of the handle's GEMM engine
+  const void* Sx() const {
+    switch (prob.precision) {
+      case KKTDD_FP64: return Sx64;
+      case KKTDD_FP32: return Sx32;
+      default: return SxBF;
+    }
+  }
+  const void* Sy() const {
+    switch (prob.precision) {
+      case KKTDD_FP64: return Sy64;
+      case KKTDD_FP32: return Sy32;
+      default: return SyBF;
+    }
+  }
   const void* invlam() const {
-    return prob.precision == KKTDD_FP32 ? (const void*)invlam32 : (const void*)invlam64;
+    return prob.precision == KKTDD_FP64 ? (const void*)invlam64 : (const void*)invlam32;
   }
 };
 
@@ -166,18 +181,20 @@ int validate(const kktdd_problem* p) {
   if (p->overlap < 0 || p->overlap > k) return bad("overlap must satisfy 0 <= overlap <= nt/n_sub");
   if (p->coarse < 0 || p->coarse > 2) return bad("coarse must be 0, 1 or 2");
   if (p->coarse == 2 && k < 2) return bad("a linear coarse basis needs nt/n_sub >= 2");
-  if (p->precision != KKTDD_FP64 && p->precision != KKTDD_FP32) return bad("unknown precision");
+  if (p->precision < KKTDD_FP64 || p->precision > KKTDD_BF16X6) return bad("unknown precision");
   if (p->sweep != KKTDD_SWEEP_STEP && p->sweep != KKTDD_SWEEP_MODAL) return bad("unknown sweep placement");
   if ((long long)p->nt * (p->nx - 1) * (p->ny - 1) > (1LL << 40)) return bad("problem too large");
   return KKTDD_OK;
 }
 
+bool is_bf16(int precision) { return precision >= KKTDD_BF16 && precision <= KKTDD_BF16X6; }
+
 Geom make_geom(const kktdd_problem& p) {
   Geom g{};
   g.mx = p.nx - 1;
   g.my = p.ny - 1;
-  g.Mx = pad_extent(g.mx);
-  g.My = pad_extent(g.my);
+  g.Mx = pad_extent(g.mx, is_bf16(p.precision));
+  g.My = pad_extent(g.my, is_bf16(p.precision));
   g.nt = p.nt;
   g.nxy = g.mx * g.my;
   g.P = (long long)g.nt * g.nxy;
@@ -210,20 +227,22 @@ constexpr int kModalRegSteps = 32;   // must match the register sweep length in 
 
 // Which buffers a configuration needs.  The coarse level runs in physical space (its own
 // float64 transforms of 2N_D slices, r' formed pointwise in float64) for the per-step sweeps
-// and for the float32 modal sweeps: float32 transforms of r itself would round r before the
-// cancellation in r - S_hat c.  Float64 modal sweeps do the coarse level in mode space.
+// and for the reduced-precision modal sweeps: float32 or bfloat16 transforms of r itself would
+// round r before the cancellation in r - S_hat c.  Float64 modal sweeps do the coarse level in
+// mode space.
 bool physical_coarse(const Geom& g, int precision, int sweep) {
-  return g.nb > 0 && (sweep == KKTDD_SWEEP_STEP || precision == KKTDD_FP32);
+  return g.nb > 0 && (sweep == KKTDD_SWEEP_STEP || precision != KKTDD_FP64);
 }
 bool needs_rprime(const Geom& g, int precision, int sweep) {
   return sweep == KKTDD_SWEEP_STEP || physical_coarse(g, precision, sweep);
 }
 
 Plan plan(const Geom& g, int precision, int sweep, int R) {
-  const size_t el = precision == KKTDD_FP32 ? 4 : 8;
+  const size_t el = precision == KKTDD_FP64 ? 8 : 4;
   const size_t MM = (size_t)g.padded();
   Plan p{};
   p.tables = ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My + MM) * 12 + (size_t)(g.mx + g.my) * 8;
+  if (is_bf16(precision)) p.tables += ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My) * 6;
   if (sweep == KKTDD_SWEEP_MODAL) {
     p.sweeps = 2 * (size_t)g.nt * MM * el;
     if (g.L > kModalRegSteps) p.sweeps += (size_t)g.nd * g.L * MM * 8;
@@ -239,6 +258,21 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
   p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
   if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
   return p;
+}
+
+// bfloat16 of a value: round its float32 image to nearest-even on the upper 16 bits.
+uint16_t bf16_round(double v) {
+  const float f = (float)v;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
 }
 
 // sin(pi * r / n) with r reduced modulo 2n first, so the argument stays in [0, 2 pi)
@@ -272,6 +306,26 @@ int build_tables(kktdd_handle* H) {
   for (int q = 0; q < g.my; ++q)
     for (int a = 0; a < g.mx; ++a) inv[(size_t)q * g.Mx + a] = norm / (g.sigma + ly[q] + lx[a]);
   auto to32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+  if (is_bf16(p.precision)) {
+    auto parts = [](const std::vector<double>& S) {
+      const size_t n = S.size();
+      std::vector<uint16_t> out(3 * n);
+      for (size_t i = 0; i < n; ++i) {
+        double rest = S[i];
+        for (int q = 0; q < 3; ++q) {
+          const uint16_t b = bf16_round(rest);
+          out[q * n + i] = b;
+          rest -= bf16_value(b);
+        }
+      }
+      return out;
+    };
+    const std::vector<uint16_t> bx = parts(Sx), by = parts(Sy);
+    if (int e = dalloc(H, &H->SxBF, bx.size())) return e;
+    if (int e = dalloc(H, &H->SyBF, by.size())) return e;
+    KKT_HIP(hipMemcpy(H->SxBF, bx.data(), bx.size() * 2, hipMemcpyHostToDevice));
+    KKT_HIP(hipMemcpy(H->SyBF, by.data(), by.size() * 2, hipMemcpyHostToDevice));
+  }
 
   if (int e = dalloc(H, &H->Sx64, Sx.size())) return e;
   if (int e = dalloc(H, &H->Sy64, Sy.size())) return e;
@@ -469,7 +523,7 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
   H->prob = *prob;
   H->g = make_geom(*prob);
   H->stream = static_cast<hipStream_t>(hip_stream);
-  H->elem = prob->precision == KKTDD_FP32 ? 4 : 8;
+  H->elem = prob->precision == KKTDD_FP64 ? 8 : 4;
   auto fail = [&](int code) {
     kkt_destroy(H);
     return code;

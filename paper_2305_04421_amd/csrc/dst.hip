@@ -15,11 +15,19 @@
 // row kernel (b_{j+1} = r'_{j+1} + y_j is formed row-locally), so one step costs one row and
 // one column launch, each doing two chained 16 x M x M GEMMs.
 //
-// MFMA: 16x16x4 (f64 or f32).  Lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
-// element r (0..3) holds D[row][l%16] with row = 4*(l/16)+r for f32 and row = l/16 + 4*r for
-// f64 (checked on gfx950).  The sine matrices are read straight from
-// L2 (they are shared by every workgroup) using their symmetry so that each MFMA operand load
-// is four 64-byte or 128-byte row segments; the other operand sits in LDS.
+// GEMM engines (one per arithmetic):
+//   f64, f32      16x16x4 MFMA.  Lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
+//                 element r holds D[row][l%16], row = 4*(l/16)+r (f32) or l/16 + 4*r (f64).
+//   bf16 x1/x3/x6 16x16x32 bf16 MFMA with float32 accumulation.  Lane l supplies
+//                 A[l%16][8*(l/16)+i] and B[8*(l/16)+i][l%16], i = 0..7; D as for f32.  A
+//                 float32 operand a is split into bfloat16 parts a0 + a1 + a2 (each part the
+//                 rounded remainder of the previous ones) and a product is accumulated from
+//                 the part products a0b0 (x1); a0b0 + a0b1 + a1b0 (x3); and those plus
+//                 a0b2 + a1b1 + a2b0 (x6) (Henry, Tang, Heinecke, ARITH 2019).
+// All layouts were checked on gfx950.  The sine matrices (pre-split into bf16 parts for the
+// bf16 engines) are read straight from L2 using their symmetry, so every operand load is a
+// run of contiguous row segments; the other operand sits in LDS.  Work buffers are float64
+// for the f64 engine and float32 otherwise.
 #include <cstdlib>
 
 #include "internal.h"
@@ -30,6 +38,7 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 template <typename T> struct AccT;
 template <> struct AccT<double> { using type = v4d; };
@@ -41,75 +50,227 @@ __device__ inline v4d mfma16(double a, double b, v4d c) {
 __device__ inline v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+__device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
-// Row (within the 16x16 tile) of accumulator element r in lane group lk = l/16.
-template <typename T> __device__ inline int acc_row(int lk, int r);
-template <> __device__ inline int acc_row<float>(int lk, int r) { return 4 * lk + r; }
-template <> __device__ inline int acc_row<double>(int lk, int r) { return lk + 4 * r; }
-
-// ---- tile GEMMs ------------------------------------------------------------------------
 // Work split inside a workgroup: the M/16 column (or row) tiles of a 16-wide block are dealt
 // to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
 // that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
-// kPD k-steps ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.
+// ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.
 constexpr int kPD = 4;
 
-// acc[t] += A (16 x M, in LDS with row stride lda) * S(:, tile wave + t*nw), S symmetric M x M.
-template <typename T, int TPW, typename Acc>
-__device__ inline void gemm_right(const T* A, int lda, const T* __restrict__ S, int M, int wave,
-                                  int nw, int li, int lk, Acc (&acc)[TPW]) {
-  const T* Sp = S + (long long)lk * M + wave * 16 + li;
-  const long long tstride = (long long)nw * 16;
-  T bq[kPD][TPW];
+// ---- plain engines (f64, f32) ----------------------------------------------------------
+template <typename T>
+struct EngPlain {
+  using data_t = T;
+  using acc_t = typename AccT<T>::type;
+  using s_t = T;
+  static __host__ __device__ size_t rows_lds(int M) { return (size_t)16 * (M + 1) * sizeof(T); }
+  static __host__ __device__ size_t cols_lds(int M) { return (size_t)M * 17 * sizeof(T); }
+  static __device__ int acc_row(int lk, int r) {
+    if constexpr (sizeof(T) == 8) return lk + 4 * r; else return 4 * lk + r;
+  }
+  // rows operand A[16][M+1]
+  static __device__ void put_a(unsigned char* lds, int M, int r, int c, T v) {
+    reinterpret_cast<T*>(lds)[r * (M + 1) + c] = v;
+  }
+  // cols operand B[M][17]
+  static __device__ void put_b(unsigned char* lds, int M, int k, int c, T v) {
+    (void)M;
+    reinterpret_cast<T*>(lds)[k * 17 + c] = v;
+  }
+  // acc[t] += A (16 x M) * S(:, tile wave + t*nw), S symmetric M x M.
+  template <int TPW>
+  static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ S, int M,
+                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    const T* A = reinterpret_cast<const T*>(lds);
+    const int lda = M + 1;
+    const T* Sp = S + (long long)lk * M + wave * 16 + li;
+    const long long tstride = (long long)nw * 16;
+    T bq[kPD][TPW];
 #pragma unroll
-  for (int p = 0; p < kPD; ++p)
+    for (int p = 0; p < kPD; ++p)
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
-  const int nks = M >> 2;
-  for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+      for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+    const int nks = M >> 2;
+    for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
-    for (int p = 0; p < kPD; ++p) {
-      const int ks = ks0 + p;
-      const T a = A[li * lda + 4 * ks + lk];
+      for (int p = 0; p < kPD; ++p) {
+        const int ks = ks0 + p;
+        const T a = A[li * lda + 4 * ks + lk];
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
-      const int kn = ks + kPD;
-      if (kn < nks) {
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
+        const int kn = ks + kPD;
+        if (kn < nks) {
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+          for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+        }
       }
     }
   }
-}
+  // acc[t] += S(row tile wave + t*nw, :) * B (M x 16).
+  template <int TPW>
+  static __device__ void gemm_left(const T* __restrict__ S, const unsigned char* lds, int M,
+                                   int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    const T* B = reinterpret_cast<const T*>(lds);
+    // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
+    const T* Sp = S + (long long)lk * M + wave * 16 + li;
+    const long long tstride = (long long)nw * 16;
+    T aq[kPD][TPW];
+#pragma unroll
+    for (int p = 0; p < kPD; ++p)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+    const int nks = M >> 2;
+    for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+#pragma unroll
+      for (int p = 0; p < kPD; ++p) {
+        const int ks = ks0 + p;
+        const T b = B[(4 * ks + lk) * 17 + li];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
+        const int kn = ks + kPD;
+        if (kn < nks) {
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+        }
+      }
+    }
+  }
+};
 
-// acc[t] += S(row tile wave + t*nw, :) * B (M x 16, in LDS with row stride ldb).
-template <typename T, int TPW, typename Acc>
-__device__ inline void gemm_left(const T* __restrict__ S, const T* B, int ldb, int M, int wave,
-                                 int nw, int li, int lk, Acc (&acc)[TPW]) {
-  // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
-  const T* Sp = S + (long long)lk * M + wave * 16 + li;
-  const long long tstride = (long long)nw * 16;
-  T aq[kPD][TPW];
+// ---- split-bfloat16 engines -------------------------------------------------------------
+template <int SPLIT>
+struct EngBF {
+  static constexpr int NP = SPLIT == 1 ? 1 : (SPLIT == 3 ? 2 : 3);   // parts per operand
+  using data_t = float;
+  using acc_t = v4f;
+  using s_t = __bf16;    // NP parts of an M x M matrix, part p at offset p*M*M
+  static __host__ __device__ size_t rows_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
+  static __host__ __device__ size_t cols_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
+  static __device__ int acc_row(int lk, int r) { return 4 * lk + r; }
+  static __device__ void split(float v, __bf16 (&part)[NP]) {
+    part[0] = (__bf16)v;
+    if constexpr (NP > 1) {
+      const float r1 = v - (float)part[0];
+      part[1] = (__bf16)r1;
+      if constexpr (NP > 2) part[2] = (__bf16)(r1 - (float)part[1]);
+    }
+  }
+  // rows operand: NP arrays A_p[16][M+8] (k contiguous)
+  static __device__ void put_a(unsigned char* lds, int M, int r, int c, float v) {
+    __bf16 part[NP];
+    split(v, part);
+    __bf16* A = reinterpret_cast<__bf16*>(lds);
 #pragma unroll
-  for (int p = 0; p < kPD; ++p)
+    for (int p = 0; p < NP; ++p) A[(p * 16 + r) * (M + 8) + c] = part[p];
+  }
+  // cols operand stored transposed: NP arrays Bt_p[16][M+8], Bt_p[c][k] = part_p(B[k][c])
+  static __device__ void put_b(unsigned char* lds, int M, int k, int c, float v) {
+    __bf16 part[NP];
+    split(v, part);
+    __bf16* B = reinterpret_cast<__bf16*>(lds);
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
-  const int nks = M >> 2;
-  for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+    for (int p = 0; p < NP; ++p) B[(p * 16 + c) * (M + 8) + k] = part[p];
+  }
+  static __device__ v4f mma(const bf16x8 (&a)[NP], const bf16x8 (&b)[NP], v4f acc) {
+    if constexpr (SPLIT == 6) {
+      acc = mfma_bf(a[2], b[0], acc);
+      acc = mfma_bf(a[1], b[1], acc);
+      acc = mfma_bf(a[0], b[2], acc);
+    }
+    if constexpr (SPLIT >= 3) {
+      acc = mfma_bf(a[1], b[0], acc);
+      acc = mfma_bf(a[0], b[1], acc);
+    }
+    return mfma_bf(a[0], b[0], acc);
+  }
+  static constexpr int ring(int TPW) { return TPW * NP <= 8 ? 2 : 1; }
+  // acc[t] += A (16 x M) * S(:, tile wave + t*nw); the B fragment of tile ct is
+  // S[32ks + 8lk + i][ct*16 + li] = S[ct*16 + li][32ks + 8lk + i]: 16 contiguous bytes.
+  template <int TPW>
+  static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ S, int M,
+                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    constexpr int RD = ring(TPW);
+    const __bf16* A = reinterpret_cast<const __bf16*>(lds);
+    const long long MM = (long long)M * M;
+    const int lda = M + 8;
+    auto bload = [&](int ks, int t, int p) {
+      const long long row = (long long)(wave + t * nw) * 16 + li;
+      return *reinterpret_cast<const bf16x8*>(S + p * MM + row * M + 32 * ks + 8 * lk);
+    };
+    bf16x8 bq[RD][TPW][NP];
 #pragma unroll
-    for (int p = 0; p < kPD; ++p) {
-      const int ks = ks0 + p;
-      const T b = B[(4 * ks + lk) * ldb + li];
+    for (int d = 0; d < RD; ++d)
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
-      const int kn = ks + kPD;
-      if (kn < nks) {
+      for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+        for (int p = 0; p < NP; ++p) bq[d][t][p] = bload(d, t, p);
+    const int nks = M >> 5;
+    for (int ks0 = 0; ks0 < nks; ks0 += RD) {
+#pragma unroll
+      for (int d = 0; d < RD; ++d) {
+        const int ks = ks0 + d;
+        if (ks >= nks) break;
+        bf16x8 af[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          af[p] = *reinterpret_cast<const bf16x8*>(A + (p * 16 + li) * lda + 32 * ks + 8 * lk);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mma(af, bq[d][t], acc[t]);
+        const int kn = ks + RD;
+        if (kn < nks) {
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) bq[d][t][p] = bload(kn, t, p);
+        }
       }
     }
   }
-}
+  // acc[t] += S(row tile wave + t*nw, :) * B (M x 16, stored transposed in LDS).
+  template <int TPW>
+  static __device__ void gemm_left(const __bf16* __restrict__ S, const unsigned char* lds, int M,
+                                   int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    constexpr int RD = ring(TPW);
+    const __bf16* Bt = reinterpret_cast<const __bf16*>(lds);
+    const long long MM = (long long)M * M;
+    const int ldb = M + 8;
+    auto aload = [&](int ks, int t, int p) {
+      const long long row = (long long)(wave + t * nw) * 16 + li;
+      return *reinterpret_cast<const bf16x8*>(S + p * MM + row * M + 32 * ks + 8 * lk);
+    };
+    bf16x8 aq[RD][TPW][NP];
+#pragma unroll
+    for (int d = 0; d < RD; ++d)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int p = 0; p < NP; ++p) aq[d][t][p] = aload(d, t, p);
+    const int nks = M >> 5;
+    for (int ks0 = 0; ks0 < nks; ks0 += RD) {
+#pragma unroll
+      for (int d = 0; d < RD; ++d) {
+        const int ks = ks0 + d;
+        if (ks >= nks) break;
+        bf16x8 bf[NP];
+#pragma unroll
+        for (int p = 0; p < NP; ++p)
+          bf[p] = *reinterpret_cast<const bf16x8*>(Bt + (p * 16 + li) * ldb + 32 * ks + 8 * lk);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mma(aq[d][t], bf, acc[t]);
+        const int kn = ks + RD;
+        if (kn < nks) {
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+#pragma unroll
+            for (int p = 0; p < NP; ++p) aq[d][t][p] = aload(kn, t, p);
+        }
+      }
+    }
+  }
+};
 
 // ---- row kernel ------------------------------------------------------------------------
 // One workgroup = 16 rows of one slice.  Optional GEMM1 (y = g1_scale * U S_x) with its
@@ -119,7 +280,7 @@ enum OutMode { OUT_NONE = 0, OUT_OWNED = 1, OUT_PLAIN = 2 };
 
 template <typename T>
 struct RowArgs {
-  const T* Sx;
+  const void* Sx;            // engine's sine-matrix operand
   const T* g1_in;            // padded slices (nullptr: y = 0)
   long long g1_stride;
   double g1_scale;
@@ -139,13 +300,15 @@ struct RowArgs {
   long long g2_stride;
 };
 
-template <typename T, int TPW>
+template <typename Eng, int TPW>
 __global__ void __launch_bounds__(512)
-k_rows(Geom g, RowArgs<T> a) {
-  using acc_t = typename AccT<T>::type;
+k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
+  using T = typename Eng::data_t;
+  using acc_t = typename Eng::acc_t;
+  using S_t = typename Eng::s_t;
   extern __shared__ unsigned char smem_raw[];
-  T* A = reinterpret_cast<T*>(smem_raw);          // [16][Mx+1]
-  const int Mx = g.Mx, lda = Mx + 1;
+  const int Mx = g.Mx;
+  const S_t* Sx = static_cast<const S_t*>(a.Sx);
   const int rb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -167,7 +330,7 @@ k_rows(Geom g, RowArgs<T> a) {
       const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rb * 16 + acc_row<T>(lk, r);
+        const int row = rb * 16 + Eng::acc_row(lk, r);
         const bool in = row < g.my && col < g.mx;
         T v = 0;
         if (a.b_mode == B_RPRIME_PLUS_Y) {
@@ -185,9 +348,9 @@ k_rows(Geom g, RowArgs<T> a) {
   // ---- GEMM1: y = U S_x ------------------------------------------------------------------
   if (a.g1_in) {
     const T* src = a.g1_in + s * a.g1_stride + (long long)rb * 16 * Mx;
-    for (int e = threadIdx.x; e < 16 * Mx; e += nthr) A[(e / Mx) * lda + e % Mx] = src[e];
+    for (int e = threadIdx.x; e < 16 * Mx; e += nthr) Eng::put_a(smem_raw, Mx, e / Mx, e % Mx, src[e]);
     __syncthreads();
-    gemm_right<T, TPW>(A, lda, a.Sx, Mx, wave, nw, li, lk, acc);
+    Eng::template gemm_right<TPW>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -203,7 +366,7 @@ k_rows(Geom g, RowArgs<T> a) {
       const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = rb * 16 + acc_row<T>(lk, r);
+        const int row = rb * 16 + Eng::acc_row(lk, r);
         const T v = acc[t][r];
         if (a.ystore) a.ystore[s * a.ystore_stride + (long long)row * Mx + col] = v;
         if (row < g.my && col < g.mx) {
@@ -233,7 +396,7 @@ k_rows(Geom g, RowArgs<T> a) {
   if (a.b_mode == B_NONE) return;
 
   // ---- form b (row-local) into LDS -------------------------------------------------------
-  __syncthreads();  // every wave has finished reading A for GEMM1
+  __syncthreads();  // every wave has finished reading the LDS operand of GEMM1
   {
     const T hT = (T)g.h;
 #pragma unroll
@@ -241,15 +404,15 @@ k_rows(Geom g, RowArgs<T> a) {
       const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int rloc = acc_row<T>(lk, r);
+        const int rloc = Eng::acc_row(lk, r);
         T b = 0;
         switch (a.b_mode) {
-          case B_RPRIME_PLUS_Y: b = pre[t][r] + acc[t][r]; break;
-          case B_H_YBUF_PLUS_Y: b = hT * pre[t][r] + acc[t][r]; break;
-          case B_H_Y: b = hT * acc[t][r]; break;
+          case B_RPRIME_PLUS_Y: b = pre[t][r] + (T)acc[t][r]; break;
+          case B_H_YBUF_PLUS_Y: b = hT * pre[t][r] + (T)acc[t][r]; break;
+          case B_H_Y: b = hT * (T)acc[t][r]; break;
           case B_INPUT: b = pre[t][r]; break;
         }
-        A[rloc * lda + col] = b;
+        Eng::put_a(smem_raw, Mx, rloc, col, b);
       }
     }
   }
@@ -258,14 +421,14 @@ k_rows(Geom g, RowArgs<T> a) {
   // ---- GEMM2: T = b S_x ------------------------------------------------------------------
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  gemm_right<T, TPW>(A, lda, a.Sx, Mx, wave, nw, li, lk, acc);
+  Eng::template gemm_right<TPW>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int col = (wave + t * nw) * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int row = rb * 16 + acc_row<T>(lk, r);
-      a.g2_out[s * a.g2_stride + (long long)row * Mx + col] = acc[t][r];
+      const int row = rb * 16 + Eng::acc_row(lk, r);
+      a.g2_out[s * a.g2_stride + (long long)row * Mx + col] = (T)acc[t][r];
     }
   }
 }
@@ -275,7 +438,7 @@ k_rows(Geom g, RowArgs<T> a) {
 // U = S_y X chained through LDS.
 template <typename T>
 struct ColArgs {
-  const T* Sy;
+  const void* Sy;      // engine's sine-matrix operand
   const T* in;
   long long in_stride;
   const T* invlam;     // nullptr: no scaling
@@ -284,41 +447,44 @@ struct ColArgs {
   long long out_stride;
 };
 
-template <typename T, int TPW>
+template <typename Eng, int TPW>
 __global__ void __launch_bounds__(512)
-k_cols(Geom g, ColArgs<T> a) {
-  using acc_t = typename AccT<T>::type;
+k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
+  using T = typename Eng::data_t;
+  using acc_t = typename Eng::acc_t;
+  using S_t = typename Eng::s_t;
   extern __shared__ unsigned char smem_raw[];
-  T* B = reinterpret_cast<T*>(smem_raw);          // [My][17]
-  constexpr int ldb = 17;
   const int Mx = g.Mx, My = g.My;
+  const S_t* Sy = static_cast<const S_t*>(a.Sy);
   const int cb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
 
   const T* src = a.in + s * a.in_stride + cb * 16;
-  for (int e = threadIdx.x; e < My * 16; e += nthr) B[(e >> 4) * ldb + (e & 15)] = src[(long long)(e >> 4) * Mx + (e & 15)];
+  for (int e = threadIdx.x; e < My * 16; e += nthr)
+    Eng::put_b(smem_raw, My, e >> 4, e & 15, src[(long long)(e >> 4) * Mx + (e & 15)]);
   __syncthreads();
 
   acc_t acc[TPW];
   for (int pass = 0; pass < 1 + a.two; ++pass) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    gemm_left<T, TPW>(a.Sy, B, ldb, My, wave, nw, li, lk, acc);
+    Eng::template gemm_left<TPW>(Sy, smem_raw, My, wave, nw, li, lk, acc);
     if (pass == 0 && a.invlam) {
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc[t][r] *= a.invlam[(long long)((wave + t * nw) * 16 + acc_row<T>(lk, r)) * Mx + cb * 16 + li];
+          acc[t][r] *= a.invlam[(long long)((wave + t * nw) * 16 + Eng::acc_row(lk, r)) * Mx + cb * 16 + li];
     }
     if (pass == 0 && a.two) {
       __syncthreads();
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) B[((wave + t * nw) * 16 + acc_row<T>(lk, r)) * ldb + li] = acc[t][r];
+        for (int r = 0; r < 4; ++r)
+          Eng::put_b(smem_raw, My, (wave + t * nw) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
       __syncthreads();
     }
   }
@@ -327,7 +493,7 @@ k_cols(Geom g, ColArgs<T> a) {
   for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      dst[(long long)((wave + t * nw) * 16 + acc_row<T>(lk, r)) * Mx + li] = acc[t][r];
+      dst[(long long)((wave + t * nw) * 16 + Eng::acc_row(lk, r)) * Mx + li] = (T)acc[t][r];
 }
 
 // ---- launch helpers ----------------------------------------------------------------------
@@ -360,24 +526,26 @@ int allow_lds(F* kernel, size_t lds) {
 }
 
 // Algorithmic flops of one launch: 2*my*mx*mx per right product, 2*my*my*mx per left product.
-template <typename T, int TPW>
-int rows_t(const Geom& g, const RowArgs<T>& a, int nslices, int nw, int kclass, hipStream_t s) {
-  const size_t lds = (size_t)16 * (g.Mx + 1) * sizeof(T);
-  if (int e = allow_lds(k_rows<T, TPW>, lds)) return e;
+template <typename Eng, int TPW>
+int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
+           hipStream_t s) {
+  const size_t lds = Eng::rows_lds(g.Mx);
+  if (int e = allow_lds(k_rows<Eng, TPW>, lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_rows<T, TPW>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  hipLaunchKernelGGL((k_rows<Eng, TPW>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, 2.0 * ngemm * nslices * (double)g.my * g.mx * g.mx);
   return 0;
 }
 
-template <typename T, int TPW>
-int cols_t(const Geom& g, const ColArgs<T>& a, int nslices, int nw, int kclass, hipStream_t s) {
-  const size_t lds = (size_t)g.My * 17 * sizeof(T);
-  if (int e = allow_lds(k_cols<T, TPW>, lds)) return e;
+template <typename Eng, int TPW>
+int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
+           hipStream_t s) {
+  const size_t lds = Eng::cols_lds(g.My);
+  if (int e = allow_lds(k_cols<Eng, TPW>, lds)) return e;
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_cols<T, TPW>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  hipLaunchKernelGGL((k_cols<Eng, TPW>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, 2.0 * (1 + a.two) * nslices * (double)g.my * g.my * g.mx);
   return 0;
@@ -385,25 +553,25 @@ int cols_t(const Geom& g, const ColArgs<T>& a, int nslices, int nw, int kclass, 
 
 #define KKT_TPW_DISPATCH(FN, TPWV, ...)                  \
   switch (TPWV) {                                        \
-    case 1: return FN<T, 1>(__VA_ARGS__);                \
-    case 2: return FN<T, 2>(__VA_ARGS__);                \
-    case 3: return FN<T, 3>(__VA_ARGS__);                \
-    case 4: return FN<T, 4>(__VA_ARGS__);                \
-    case 5: return FN<T, 5>(__VA_ARGS__);                \
-    case 6: return FN<T, 6>(__VA_ARGS__);                \
-    case 7: return FN<T, 7>(__VA_ARGS__);                \
-    case 8: return FN<T, 8>(__VA_ARGS__);                \
+    case 1: return FN<Eng, 1>(__VA_ARGS__);              \
+    case 2: return FN<Eng, 2>(__VA_ARGS__);              \
+    case 3: return FN<Eng, 3>(__VA_ARGS__);              \
+    case 4: return FN<Eng, 4>(__VA_ARGS__);              \
+    case 5: return FN<Eng, 5>(__VA_ARGS__);              \
+    case 6: return FN<Eng, 6>(__VA_ARGS__);              \
+    case 7: return FN<Eng, 7>(__VA_ARGS__);              \
+    case 8: return FN<Eng, 8>(__VA_ARGS__);              \
     default: return set_error(KKTDD_EINVAL, "unsupported tile count"); \
   }
 
-template <typename T>
-int rows(const Geom& g, const RowArgs<T>& a, int nslices, int kclass, hipStream_t s) {
+template <typename Eng>
+int rows(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.Mx);
   KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / nw, g, a, nslices, nw, kclass, s)
 }
 
-template <typename T>
-int cols(const Geom& g, const ColArgs<T>& a, int nslices, int kclass, hipStream_t s) {
+template <typename Eng>
+int cols(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
   const int nw = waves_for(g.My);
   KKT_TPW_DISPATCH(cols_t, g.My / 16 / nw, g, a, nslices, nw, kclass, s)
 }
@@ -411,47 +579,49 @@ int cols(const Geom& g, const ColArgs<T>& a, int nslices, int kclass, hipStream_
 template <typename T>
 RowArgs<T> row_args(const void* Sx) {
   RowArgs<T> a{};
-  a.Sx = static_cast<const T*>(Sx);
+  a.Sx = Sx;
   a.g1_scale = 1.0;
   return a;
 }
 
-template <typename T>
+template <typename Eng>
 int spatial_solve_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
                     const double* b, double* x, int nslices, void* w1, void* w2, hipStream_t s) {
+  using T = typename Eng::data_t;
   const long long MM = g.padded();
   RowArgs<T> r1 = row_args<T>(Sx);
   r1.b_mode = B_INPUT;
   r1.rin = b;
   r1.g2_out = static_cast<T*>(w1);
   r1.g2_stride = MM;
-  if (int e = rows<T>(g, r1, nslices, KKTDD_K_OTHER, s)) return e;
-  ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(w1), MM,
+  if (int e = rows<Eng>(g, r1, nslices, KKTDD_K_OTHER, s)) return e;
+  ColArgs<T> c{Sy, static_cast<const T*>(w1), MM,
                static_cast<const T*>(invlam), 1, static_cast<T*>(w2), MM};
-  if (int e = cols<T>(g, c, nslices, KKTDD_K_OTHER, s)) return e;
+  if (int e = cols<Eng>(g, c, nslices, KKTDD_K_OTHER, s)) return e;
   RowArgs<T> r2 = row_args<T>(Sx);
   r2.g1_in = static_cast<const T*>(w2);
   r2.g1_stride = MM;
   r2.out_mode = OUT_PLAIN;
   r2.out64 = x;
-  return rows<T>(g, r2, nslices, KKTDD_K_OTHER, s);
+  return rows<Eng>(g, r2, nslices, KKTDD_K_OTHER, s);
 }
 
 // RASQ sweeps (Eq. (13)) of all subdomains in lockstep.  Subdomain s (0-based) covers the
 // nodes s*k+1-delta .. (s+1)*k (sweep steps j = 0..L-1, L = k+delta); for s = 0 the nodes
 // below 1 carry a zero right-hand side, which keeps the state exactly zero there, so every
 // subdomain runs the same L steps.
-template <typename T>
+template <typename Eng>
 int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
              const double* rprime, const double* c0, double* zw, void* Tb, void* Ub, void* Yb,
              hipStream_t s) {
+  using T = typename Eng::data_t;
   const long long MM = g.padded();
   T* Tbuf = static_cast<T*>(Tb);
   T* Ubuf = static_cast<T*>(Ub);
   T* Ybuf = static_cast<T*>(Yb);
   const long long ystride = (long long)g.L * MM;
   const int nd = g.nd, L = g.L;
-  ColArgs<T> c{static_cast<const T*>(Sy), Tbuf, MM, static_cast<const T*>(invlam), 1, Ubuf, MM};
+  ColArgs<T> c{Sy, Tbuf, MM, static_cast<const T*>(invlam), 1, Ubuf, MM};
 
   // forward sweep: y_j = D^{-1}(r'_j + y_{j-1})
   for (int j = 0; j < L; ++j) {
@@ -467,8 +637,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.rin = rprime;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
-    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
+    if (int e = rows<Eng>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<Eng>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   // junction: y_{L-1} from the last solve; adjoint right-hand side h*y_{L-1}
   {
@@ -478,8 +648,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.b_mode = B_H_Y;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
-    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
+    if (int e = rows<Eng>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<Eng>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   // adjoint sweep: x_j = D^{-1}(h y_j + x_{j+1}); owned x_{j+1} written with the coarse part
   for (int j = L - 2; j >= 0; --j) {
@@ -496,8 +666,8 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     r.ybuf_stride = ystride;
     r.g2_out = Tbuf;
     r.g2_stride = MM;
-    if (int e = rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
-    if (int e = cols<T>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
+    if (int e = rows<Eng>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
+    if (int e = cols<Eng>(g, c, nd, KKTDD_K_SWEEP_COLS, s)) return e;
   }
   RowArgs<T> r = row_args<T>(Sx);
   r.g1_in = Ubuf;
@@ -507,12 +677,13 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
   r.c0 = c0;
   r.g1_step = 0;
   r.b_mode = B_NONE;
-  return rows<T>(g, r, nd, KKTDD_K_SWEEP_ROWS, s);
+  return rows<Eng>(g, r, nd, KKTDD_K_SWEEP_ROWS, s);
 }
 
-template <typename T>
+template <typename Eng>
 int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* in,
                   const double* dscale, void* tmp, void* out, int nslices, hipStream_t s) {
+  using T = typename Eng::data_t;
   const long long MM = g.padded();
   RowArgs<T> r = row_args<T>(Sx);
   r.b_mode = B_INPUT;
@@ -520,19 +691,20 @@ int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* i
   r.in_scale = dscale;
   r.g2_out = static_cast<T*>(tmp);
   r.g2_stride = MM;
-  if (int e = rows<T>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s)) return e;
-  ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(tmp), MM, nullptr, 0,
+  if (int e = rows<Eng>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s)) return e;
+  ColArgs<T> c{Sy, static_cast<const T*>(tmp), MM, nullptr, 0,
                static_cast<T*>(out), MM};
-  return cols<T>(g, c, nslices, KKTDD_K_SWEEP_COLS, s);
+  return cols<Eng>(g, c, nslices, KKTDD_K_SWEEP_COLS, s);
 }
 
-template <typename T>
+template <typename Eng>
 int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in, void* tmp,
                   double* out, int nslices, double norm, const double* c0, hipStream_t s) {
+  using T = typename Eng::data_t;
   const long long MM = g.padded();
-  ColArgs<T> c{static_cast<const T*>(Sy), static_cast<const T*>(in), MM, nullptr, 0,
+  ColArgs<T> c{Sy, static_cast<const T*>(in), MM, nullptr, 0,
                static_cast<T*>(tmp), MM};
-  if (int e = cols<T>(g, c, nslices, KKTDD_K_SWEEP_COLS, s)) return e;
+  if (int e = cols<Eng>(g, c, nslices, KKTDD_K_SWEEP_COLS, s)) return e;
   RowArgs<T> r = row_args<T>(Sx);
   r.g1_in = static_cast<const T*>(tmp);
   r.g1_stride = MM;
@@ -540,40 +712,44 @@ int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in,
   r.out_mode = OUT_PLAIN;
   r.out64 = out;
   r.c0 = c0;
-  return rows<T>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s);
+  return rows<Eng>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s);
 }
 
 }  // namespace
 
+#define KKT_ENGINE_DISPATCH(PREC, FN, ...)                                    \
+  switch (PREC) {                                                             \
+    case KKTDD_FP64: return FN<EngPlain<double>>(__VA_ARGS__);                \
+    case KKTDD_FP32: return FN<EngPlain<float>>(__VA_ARGS__);                 \
+    case KKTDD_BF16: return FN<EngBF<1>>(__VA_ARGS__);                        \
+    case KKTDD_BF16X3: return FN<EngBF<3>>(__VA_ARGS__);                      \
+    case KKTDD_BF16X6: return FN<EngBF<6>>(__VA_ARGS__);                      \
+    default: return set_error(KKTDD_EINVAL, "unknown precision");            \
+  }
+
 int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const double* in, const double* dscale, void* tmp, void* out, int nslices,
                        hipStream_t s) {
-  if (precision == KKTDD_FP32) return dst_forward_t<float>(g, Sx, Sy, in, dscale, tmp, out, nslices, s);
-  return dst_forward_t<double>(g, Sx, Sy, in, dscale, tmp, out, nslices, s);
+  KKT_ENGINE_DISPATCH(precision, dst_forward_t, g, Sx, Sy, in, dscale, tmp, out, nslices, s)
 }
 
 int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const void* in, void* tmp, double* out, int nslices, double norm,
                        const double* c0, hipStream_t s) {
-  if (precision == KKTDD_FP32) return dst_inverse_t<float>(g, Sx, Sy, in, tmp, out, nslices, norm, c0, s);
-  return dst_inverse_t<double>(g, Sx, Sy, in, tmp, out, nslices, norm, c0, s);
+  KKT_ENGINE_DISPATCH(precision, dst_inverse_t, g, Sx, Sy, in, tmp, out, nslices, norm, c0, s)
 }
 
 int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const void* Sy,
                          const void* invlam, const double* b, double* x, int nslices,
                          void* work1, void* work2, hipStream_t s) {
   if (nslices <= 0) return 0;
-  if (precision == KKTDD_FP32)
-    return spatial_solve_t<float>(g, Sx, Sy, invlam, b, x, nslices, work1, work2, s);
-  return spatial_solve_t<double>(g, Sx, Sy, invlam, b, x, nslices, work1, work2, s);
+  KKT_ENGINE_DISPATCH(precision, spatial_solve_t, g, Sx, Sy, invlam, b, x, nslices, work1, work2, s)
 }
 
 int launch_sweeps(const Geom& g, int precision, const void* Sx, const void* Sy,
                   const void* invlam, const double* rprime, const double* c0, double* zw,
                   void* Tbuf, void* Ubuf, void* Ybuf, hipStream_t s) {
-  if (precision == KKTDD_FP32)
-    return sweeps_t<float>(g, Sx, Sy, invlam, rprime, c0, zw, Tbuf, Ubuf, Ybuf, s);
-  return sweeps_t<double>(g, Sx, Sy, invlam, rprime, c0, zw, Tbuf, Ubuf, Ybuf, s);
+  KKT_ENGINE_DISPATCH(precision, sweeps_t, g, Sx, Sy, invlam, rprime, c0, zw, Tbuf, Ubuf, Ybuf, s)
 }
 
 int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const double* r0,
@@ -584,23 +760,23 @@ int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const d
   r.rin = r0;
   r.g2_out = tmp;
   r.g2_stride = MM;
-  if (int e = rows<double>(g, r, g.nc, KKTDD_K_COARSE, s)) return e;
+  if (int e = rows<EngPlain<double>>(g, r, g.nc, KKTDD_K_COARSE, s)) return e;
   ColArgs<double> c{Sy, tmp, MM, nullptr, 0, rhat, MM};
-  return cols<double>(g, c, g.nc, KKTDD_K_COARSE, s);
+  return cols<EngPlain<double>>(g, c, g.nc, KKTDD_K_COARSE, s);
 }
 
 int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
                        double* c0, double* tmp, double norm, hipStream_t s) {
   const long long MM = g.padded();
   ColArgs<double> c{Sy, chat, MM, nullptr, 0, tmp, MM};
-  if (int e = cols<double>(g, c, g.nc, KKTDD_K_COARSE, s)) return e;
+  if (int e = cols<EngPlain<double>>(g, c, g.nc, KKTDD_K_COARSE, s)) return e;
   RowArgs<double> r = row_args<double>(Sx);
   r.g1_in = tmp;
   r.g1_stride = MM;
   r.g1_scale = norm;
   r.out_mode = OUT_PLAIN;
   r.out64 = c0;
-  return rows<double>(g, r, g.nc, KKTDD_K_COARSE, s);
+  return rows<EngPlain<double>>(g, r, g.nc, KKTDD_K_COARSE, s);
 }
 
 }  // namespace kktdd

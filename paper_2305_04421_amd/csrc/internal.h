@@ -35,9 +35,11 @@ struct Geom {
 };
 
 // Padded sine-transform extent: a multiple of 16 whose tile count t = M/16 splits evenly over
-// the waves of a workgroup (t <= 8, or a multiple of 4 up to 32, or of 8 above).
-inline int pad_extent(int m) {
+// the waves of a workgroup (t <= 8, or a multiple of 4 up to 32, or of 8 above).  The bfloat16
+// engines step k by 32, so for them t is also even.
+inline int pad_extent(int m, bool even = false) {
   int t = (m + 15) / 16;
+  if (even && (t & 1)) ++t;
   if (t > 8) t = (t + 3) / 4 * 4;
   if (t > 32) t = (t + 7) / 8 * 8;
   return 16 * t;

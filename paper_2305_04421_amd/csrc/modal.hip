@@ -146,21 +146,21 @@ int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double
   const long long MM = g.padded();
   const dim3 grid((unsigned)((MM + kBlock - 1) / kBlock), g.nd);
   prof_begin(KKTDD_K_COARSE, s);
-  if (precision == KKTDD_FP32)
+  if (precision != KKTDD_FP64)
     hipLaunchKernelGGL((k_modal_restrict<float>), grid, dim3(kBlock), 0, s, g,
                        static_cast<const float*>(rhat), r0);
   else
     hipLaunchKernelGGL((k_modal_restrict<double>), grid, dim3(kBlock), 0, s, g,
                        static_cast<const double*>(rhat), r0);
   KKT_HIP(hipGetLastError());
-  prof_end(KKTDD_K_COARSE, s, (precision == KKTDD_FP32 ? 4.0 : 8.0) * MM * g.nt + 8.0 * MM * g.nc, 0.0);
+  prof_end(KKTDD_K_COARSE, s, (precision != KKTDD_FP64 ? 4.0 : 8.0) * MM * g.nt + 8.0 * MM * g.nc, 0.0);
   return 0;
 }
 
 int launch_modal_sweeps(const Geom& g, int precision, const void* rhat, const double* c0,
                         const double* lamx, const double* lamy, double* yscratch, void* zhat,
                         hipStream_t s) {
-  if (precision == KKTDD_FP32) return modal_t<float>(g, rhat, c0, lamx, lamy, yscratch, zhat, s);
+  if (precision != KKTDD_FP64) return modal_t<float>(g, rhat, c0, lamx, lamy, yscratch, zhat, s);
   return modal_t<double>(g, rhat, c0, lamx, lamy, yscratch, zhat, s);
 }
 

@@ -45,14 +45,15 @@ def _prob(**kw):
     base = dict(nx=32, ny=32, nt=32, Lx=1.0, Ly=1.0, T=1.0, nu=1.0, omega=1e-2, n_sub=4, overlap=2, coarse=2)
     base.update(kw)
     prec = base.pop("precision", "fp64")
-    return _lib.make_problem(base, prec)
+    sweep = base.pop("sweep", "step")
+    return _lib.make_problem(base, prec, sweep)
 
 
 def test_validate_accepts_the_configurations(lib):
     from paper_2305_04421_amd import workloads as wl
     for name in ("tiny32", "grid128", "grid128_w4", "grid256", "grid512"):
         params, _ = wl.config(name)
-        for prec in ("fp64", "fp32"):
+        for prec in ("fp64", "fp32", "bf16", "bf16x3", "bf16x6"):
             p = _prob(**dict(params, precision=prec))
             assert lib.kkt_validate(ctypes.byref(p)) == 0, name
 
@@ -60,7 +61,7 @@ def test_validate_accepts_the_configurations(lib):
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(nx=1025), dict(nt=0), dict(omega=0.0),
                                  dict(nu=-1.0), dict(T=float("inf")), dict(Lx=0.0), dict(n_sub=5),
                                  dict(overlap=9), dict(overlap=-1), dict(coarse=3), dict(n_sub=32, coarse=2),
-                                 dict(precision=7)])
+                                 dict(precision=7), dict(sweep=2)])
 def test_validate_rejects_bad_problems(lib, bad):
     from paper_2305_04421_amd import _lib
     p = _prob(**bad)

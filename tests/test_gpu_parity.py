@@ -71,7 +71,10 @@ def test_rhs_matches_oracle(name):
     assert relerr(f, op.rhs(p, u0, ut)) <= 1e-15
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+PRECISION_TOL = [("fp64", 1e-11), ("fp32", 1e-4), ("bf16x6", 1e-4), ("bf16x3", 1e-3), ("bf16", 5e-2)]
+
+
+@pytest.mark.parametrize("precision,tol", PRECISION_TOL)
 @pytest.mark.parametrize("name", list(CASES))
 def test_spatial_solve_matches_oracle(name, precision, tol):
     params = CASES[name]
@@ -83,7 +86,7 @@ def test_spatial_solve_matches_oracle(name, precision, tol):
 
 
 @pytest.mark.parametrize("nx,ny", [(81, 100), (200, 17), (600, 33), (1024, 9), (9, 1024), (129, 257)])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 1e-4)])
+@pytest.mark.parametrize("precision,tol", PRECISION_TOL)
 def test_spatial_solve_tile_shapes(nx, ny, precision, tol):
     """Padded extents whose tile counts need 1..8 tiles per wave and up to 8 waves, and
     workgroups needing more than 64 KiB of LDS."""
@@ -108,14 +111,15 @@ def test_precond_matches_oracle(name, coarse, sweep):
     assert relerr(z, want) <= 1e-11
 
 
+@pytest.mark.parametrize("precision,tol", PRECISION_TOL[1:])
 @pytest.mark.parametrize("sweep", ["step", "modal"])
-def test_precond_fp32_close_to_oracle(sweep):
+def test_precond_reduced_precision_close_to_oracle(sweep, precision, tol):
     params = CASES["tiny32"]
     p = Problem(**params).validate()
     r = wl.random_field((3,) + p.field_shape, 107)
-    with solver(params, "fp32", sweep=sweep) as S:
+    with solver(params, precision, sweep=sweep) as S:
         z = host(S.precond(dev(r)), r.shape)
-    assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-4
+    assert relerr(z, pc.apply_Pinv(p, r)) <= 10 * tol
 
 
 @pytest.mark.parametrize("sweep", ["step", "modal"])
@@ -178,19 +182,26 @@ def test_fgmres_converges_like_oracle_tiny32(sweep):
     assert np.linalg.norm(f - op.apply_K(p, xs)) <= 1e-8 * np.linalg.norm(f)
 
 
+# Iterations allowed above float64 for each inner precision (float64 FGMRES recovers the
+# 1e-8 residual; the inner rounding, amplified by the condition number of D_sigma, costs
+# iterations).  Plain bfloat16 only has to converge.
+EXTRA_ITERS = {"fp32": 2, "bf16x6": 2, "bf16x3": 4, "bf16": 60}
+
+
+@pytest.mark.parametrize("precision", list(EXTRA_ITERS))
 @pytest.mark.parametrize("sweep", ["step", "modal"])
-def test_fp32_sweeps_reach_same_tolerance_within_two_iterations(sweep):
+def test_reduced_precision_sweeps_reach_float64_tolerance(sweep, precision):
     params, recipe = wl.config("tiny32")
     p = Problem(**params).validate()
     u0, ut = wl.data(params, recipe)
     f = op.rhs(p, u0, ut)
-    with solver(params, "fp64", sweep=sweep) as S64, solver(params, "fp32", sweep=sweep) as S32:
+    with solver(params, "fp64", sweep=sweep) as S64, solver(params, precision, sweep=sweep) as Sr:
         fd = dev(f)
         x64, st64 = S64.solve(fd, restart=30, maxit=300, rtol=1e-8)
-        x32, st32 = S32.solve(fd, restart=30, maxit=300, rtol=1e-8)
-    assert st32["status"] == 0 and st32["iters"] <= st64["iters"] + 2
-    x32h = host(x32, f.shape)
-    assert np.linalg.norm(f - op.apply_K(p, x32h)) <= 1e-8 * np.linalg.norm(f)
+        xr, str_ = Sr.solve(fd, restart=30, maxit=300, rtol=1e-8)
+    assert str_["status"] == 0 and str_["iters"] <= st64["iters"] + EXTRA_ITERS[precision], (st64, str_)
+    xrh = host(xr, f.shape)
+    assert np.linalg.norm(f - op.apply_K(p, xrh)) <= 1e-8 * np.linalg.norm(f)
 
 
 def test_fgmres_edge_cases():
