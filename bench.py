@@ -33,12 +33,26 @@ sys.path.insert(0, ROOT)
 METRIC = "KKT space-time unknowns solved/s to 1e-8 rel. residual, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-WORKLOADS = ("grid128", "grid128_w4")
+WORKLOAD_SETS = {
+    # the two problems one step solves (one batch)
+    "grid128": ("grid128", "grid128_w4"),
+    "grid256": ("grid256",),
+    "grid512": ("grid512",),
+}
+MIXED = ("fp32", "bf16x6", "bf16x3", "bf16")
+DESCRIPTIONS = {
+    "grid128": "grid128: 127x127 interior x nt=256, T=1, nu=1, omega {1e-2, 1e-4}, 16 time subdomains, "
+               "overlap 2, constant+linear coarse basis",
+    "grid256": "grid256: 255x255 interior x nt=1024, T=1, nu=0.1, omega 1e-3, 64 time subdomains, "
+               "overlap 2, constant+linear coarse basis, target with 1e-3 noise",
+    "grid512": "grid512: 511x511 interior x nt=2048, T=1, nu=1, omega 1e-4, 128 time subdomains, "
+               "overlap 4, constant+linear coarse basis",
+}
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE (FETCH_SIZE scaled by 2.0,
 # WRITE_SIZE by 1.0: what a 1 GiB device copy reads on those counters), per kernel class, as
 # recorded in profiles/arnoldi_grid128_fp64_hbm_counters.md for the current kernels.  A class
 # whose kernels changed since the counters were taken is absent (traffic null).
-TRAFFIC = {"arnoldi": 470.10e6, "matvec": 215.89e6}
+TRAFFIC = {"matvec": 215.89e6}
 
 
 def parse():
@@ -56,6 +70,8 @@ def parse():
                     help="solve the problems of a step one after another instead of as one batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device once (a known-size kernel for HBM counters)")
+    ap.add_argument("--workload", default="grid128", choices=sorted(WORKLOAD_SETS),
+                    help="problem set of one step (default: grid128 at omega 1e-2 and 1e-4)")
     return ap.parse_args()
 
 
@@ -78,6 +94,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     probs = []
+    WORKLOADS = WORKLOAD_SETS[args.workload]
     for name in WORKLOADS:
         params, recipe = wl.config(name)
         u0, ut = wl.data(params, recipe)
@@ -139,9 +156,7 @@ def main():
         "metric": METRIC, "value": value64, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt64 / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "grid128: 127x127 interior x nt=256, T=1, nu=1, omega {1e-2, 1e-4}, "
-                               "16 time subdomains, overlap 2, constant+linear coarse basis, "
-                               "FGMRES(%d) to %g from x0=0, %s" % (
+        "config": {"workload": DESCRIPTIONS[args.workload] + ", FGMRES(%d) to %g from x0=0, %s" % (
                                    args.restart, args.rtol,
                                    "solved one after another" if args.sequential else "solved as one batch"),
                    "unknowns_per_step": sum(unknowns), "problems": list(WORKLOADS)},
@@ -173,38 +188,32 @@ def main():
     roof["timed_on"] = "one extra step, its solves run one after another, HIP events around every launch"
     result["roofline"] = roof
 
+    def summary(prec, sweep):
+        dt, st, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep)
+        v = args.steps * sum(unknowns) / dt
+        return {"value": v, "ms_per_step": 1e3 * dt / args.steps, "ratio_vs_fp64": v / value64,
+                "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
+                "relres_true": {name: x["relres_true"] for (name, _, _, _), x in zip(probs, st)}}
+
     if not args.no_mixed:
-        dt32, st32, _ = run_path("fp32", args.steps, args.warmup, profile=False)
-        value32 = args.steps * sum(unknowns) / dt32
-        result["mixed"] = {
-            "dtype": "f32 sweeps+DST GEMMs, f64 FGMRES/matvec/coarse", "value": value32,
-            "ms_per_step": 1e3 * dt32 / args.steps, "ratio_vs_fp64": value32 / value64,
-            "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st32)},
-            "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st32)},
-        }
+        # reduced-precision sweeps and sine-transform GEMMs; FGMRES, matvec and coarse level
+        # stay float64 (FGMRES acting as iterative refinement)
+        result["mixed"] = {prec: summary(prec, "step") for prec in MIXED}
 
     if not args.no_hoisted:
         # transform-hoisted Schur block (sine-mode sweeps), measured beside the per-step path
-        result["hoisted"] = {}
-        for prec in ("fp64", "fp32"):
-            dth, sth, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep="modal")
-            vh = args.steps * sum(unknowns) / dth
-            result["hoisted"][prec] = {
-                "value": vh, "ms_per_step": 1e3 * dth / args.steps, "ratio_vs_fp64_per_step": vh / value64,
-                "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, sth)},
-                "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, sth)},
-            }
+        result["hoisted"] = {prec: summary(prec, "modal") for prec in ("fp64",) + MIXED}
 
     if args.cpu_iters > 0:
-        result["cpu_baseline"] = cpu_baseline(args, probs[0][1], st64[0]["iters"])
+        result["cpu_baseline"] = cpu_baseline(args, probs[0][0], probs[0][1], st64[0]["iters"])
 
     print(json.dumps(result), flush=True)
     return 0
 
 
-def cpu_baseline(args, params, iters_full):
+def cpu_baseline(args, name, params, iters_full):
     """The CPU oracle on a bounded sample: its first `cpu_iters` FGMRES iterations of the
-    omega=1e-2 problem, scaled to the iteration count of the full solve."""
+    step's first problem, scaled to the iteration count of the full solve."""
     import numpy as np
     from oracle.problem import Problem
     from oracle import operators as op, precond as pc, gmres as gm
@@ -215,7 +224,7 @@ def cpu_baseline(args, params, iters_full):
     except Exception:
         threads = None
     p = Problem(**params).validate()
-    u0, ut = wl.data(params, wl.config("grid128")[1])
+    u0, ut = wl.data(params, wl.config(name)[1])
     f = op.rhs(p, u0, ut)
     t0 = time.perf_counter()
     res = gm.gmres(lambda v: op.apply_K(p, v), lambda v: pc.apply_Pinv(p, v), f,
@@ -225,7 +234,7 @@ def cpu_baseline(args, params, iters_full):
     unknowns = p.size
     return {"value": unknowns / (per_iter * iters_full), "unit": "unknowns/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {res.iterations} FGMRES({args.restart}) iterations of the grid128 omega=1e-2 "
+            "sample": f"first {res.iterations} FGMRES({args.restart}) iterations of the {name} "
                       f"solve ({dt:.1f} s incl. the initial residual), scaled to the {iters_full} "
                       f"iterations of the full solve; numpy float64 with {threads} BLAS threads"}
 

@@ -7,6 +7,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <algorithm>
@@ -19,7 +20,17 @@ namespace kktdd {
 
 namespace {
 thread_local std::string g_last_error;
+// Arnoldi orthogonalisation: DCGS2 (default) or, with KKTDD_ARNOLDI=cgs, classical
+// Gram-Schmidt with selective reorthogonalisation.
+bool arnoldi_dcgs2() {
+  static const bool v = [] {
+    const char* e = std::getenv("KKTDD_ARNOLDI");
+    return !(e && std::string(e) == "cgs");
+  }();
+  return v;
+}
 constexpr int kRedBlocks = 1024;   // blocks of the two-stage reductions
+constexpr int kMaxSums = 72;       // per-block partial sums of one reduction (2*31 + 3 <= 72)
 constexpr double kReorthEta = 0.70710678118654752;  // 1/sqrt(2)
 }  // namespace
 
@@ -255,7 +266,7 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
     p.coarse = (size_t)g.nc * MM * 8 * 2 + (size_t)g.nxy * g.nc * (hb + 1) * 8;
     if (physical_coarse(g, precision, sweep)) p.coarse += (size_t)g.nc * g.nxy * 8 * 4;
   }
-  p.coarse += (size_t)kRedBlocks * 40 * 8 + 64 * 8;
+  p.coarse += (size_t)kRedBlocks * kMaxSums * 8 + 128 * 8;
   if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
   return p;
 }
@@ -585,9 +596,9 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
       return fail(set_error(KKTDD_EHIP, "hipMemsetAsync failed"));
     }
   }
-  if (int e = dalloc(H, &H->partials, (size_t)kRedBlocks * 40)) return fail(e);
+  if (int e = dalloc(H, &H->partials, (size_t)kRedBlocks * kMaxSums)) return fail(e);
   if (int e = dalloc(H, &H->sums, 128)) return fail(e);
-  if (hipHostMalloc((void**)&H->host_sums, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  if (hipHostMalloc((void**)&H->host_sums, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     H->host_sums = nullptr;
     return fail(set_error(KKTDD_EHIP, "hipHostMalloc failed"));
@@ -702,7 +713,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   if (!H->hcol) {
     if (int e = dalloc(H, &H->hcol, 3 * 40)) return e;
     if (int e = dalloc(H, &H->vinv, 40)) return e;
-    if (int e = dalloc(H, &H->ydev, 40)) return e;
+    if (int e = dalloc(H, &H->ydev, 160)) return e;
     if (int e = dalloc(H, &H->gate, 1)) return e;
     if (hipHostMalloc((void**)&H->host_hcol, 3 * 40 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
       (void)hipGetLastError();
@@ -739,9 +750,46 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   const long long ldv = krylov_ld(g);
   double* V = H->V;
   double* Zw = H->Zw;
-  std::vector<double> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R);
+  const bool dcgs = arnoldi_dcgs2();
+  // Hessenberg (R+1) x R row-major, Givens rotations, rotated right-hand side
+  std::vector<double> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R), yv(R), yw(R);
+  // DCGS2: alpha[j] and amat[i*(R+1)+j] = coefficients of the candidate of step j in the
+  // final basis (candidate_j = alpha_j v_j + sum_{i<j} a_ij v_i)
+  std::vector<double> alpha(R + 1), amat((size_t)(R + 1) * (R + 1));
   double est = INFINITY;
   int its = 0, cycles = 0;
+  auto rotate_column = [&](int j) {
+    for (int i = 0; i < j; ++i) {
+      const double a = Hm[(size_t)i * R + j], b = Hm[(size_t)(i + 1) * R + j];
+      Hm[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
+      Hm[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = Hm[(size_t)j * R + j], b = Hm[(size_t)(j + 1) * R + j];
+    const double rho = std::hypot(a, b);
+    cs[j] = rho == 0.0 ? 1.0 : a / rho;
+    sn[j] = rho == 0.0 ? 0.0 : b / rho;
+    Hm[(size_t)j * R + j] = rho;
+    Hm[(size_t)(j + 1) * R + j] = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+  };
+  // provisional |g_{j+1}| if column j were cand (length j+2), without touching the state
+  auto provisional = [&](int j, const std::vector<double>& cand) {
+    std::vector<double> c(cand);
+    for (int i = 0; i < j; ++i) {
+      const double a = c[i], b = c[i + 1];
+      c[i] = cs[i] * a + sn[i] * b;
+      c[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    const double rho = std::hypot(c[j], c[j + 1]);
+    return rho == 0.0 ? 0.0 : std::fabs(c[j + 1] / rho * gv[j]);
+  };
+  auto bad = [&](const char* what) {
+    const double z3[3] = {NAN, NAN, NAN};
+    st.iters = its;
+    finish(KKTDD_EBREAKDOWN, est, z3);
+    return set_error(KKTDD_EBREAKDOWN, what);
+  };
   while (true) {
     // r = f - K x into V_0
     if (int e = launch_kkt_apply(g, x, x + g.P, x + 2 * g.P, 1.0, 1.0, 1.0, nullptr, f, V,
@@ -769,8 +817,10 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
     std::fill(Hm.begin(), Hm.end(), 0.0);
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
-    int jend = 0;
-    bool breakdown = false;
+    int m = 0;   // columns of this cycle that enter the solution
+    double* sums = H->sums;
+    double* rec = H->hcol;
+    const double* hrec = H->host_hcol;
     for (int j = 0; j < R; ++j) {
       double* vj = V + (long long)j * ldv;
       double* w = V + (long long)(j + 1) * ldv;
@@ -780,77 +830,130 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       // w = K z_j
       if (int e = launch_kkt_apply(g, vj, vj + g.P, zwj, 1.0 / g.h, 1.0 / (g.omega * g.h), 1.0,
                                    H->vinv + j, nullptr, w, w + g.P, w + 2 * g.P, s)) return e;
-      const int nv = j + 1;
-      // separate slots so the three stages do not overwrite each other
-      double* sums1 = H->sums;
-      double* sums2 = H->sums + 40;
-      double* sums3 = H->sums + 80;
-      // pass A: <v_i, w>, ||w||
-      if (int e = launch_multidot(n3, V, ldv, nv, H->vinv, w, 1, H->partials, kRedBlocks, s)) return e;
-      if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums1, s)) return e;
-      if (int e = launch_arnoldi_finish(j, sums1, nullptr, nullptr, H->gate, H->hcol, H->vinv,
-                                        kReorthEta, 1, s)) return e;
-      // pass B: w -= V h; <v_i, w1>, ||w1||
-      if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 1,
-                                    H->partials, kRedBlocks, nullptr, s)) return e;
-      if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums2, s)) return e;
-      if (int e = launch_arnoldi_finish(j, nullptr, sums2, nullptr, H->gate, H->hcol, H->vinv,
-                                        kReorthEta, 2, s)) return e;
-      // pass C (only if the gate is set): w -= V h2; ||w2||
-      const long long passC = prof_mark();
-      if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 0,
-                                    H->partials, kRedBlocks, H->gate, s)) return e;
-      if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums3, s)) return e;
-      if (int e = launch_arnoldi_finish(j, nullptr, nullptr, sums3, H->gate, H->hcol,
-                                        H->vinv, kReorthEta, 3, s)) return e;
-      KKT_HIP(hipMemcpyAsync(H->host_hcol, H->hcol, (j + 3) * sizeof(double),
-                             hipMemcpyDeviceToHost, s));
-      KKT_HIP(hipStreamSynchronize(s));
-      const double* hc = H->host_hcol;
-      if (hc[j + 2] != 0.0) {
-        ++st.reorth;
-        prof_add_bytes(passC, (double)(nv + 2) * n3 * 8.0);   // the gated pass ran
-      }
-      for (int i = 0; i <= j + 1; ++i) {
-        if (!std::isfinite(hc[i])) {
-          const double z3[3] = {NAN, NAN, NAN};
-          st.iters = its;
-          finish(KKTDD_EBREAKDOWN, est, z3);
-          return set_error(KKTDD_EBREAKDOWN, "non-finite Hessenberg entry");
+      if (!dcgs) {
+        // ---- classical Gram-Schmidt with selective reorthogonalisation ------------------
+        const int nv = j + 1;
+        double* sums1 = H->sums;
+        double* sums2 = H->sums + 40;
+        double* sums3 = H->sums + 80;
+        if (int e = launch_multidot(n3, V, ldv, nv, H->vinv, w, 1, H->partials, kRedBlocks, s)) return e;
+        if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums1, s)) return e;
+        if (int e = launch_arnoldi_finish(j, sums1, nullptr, nullptr, H->gate, H->hcol, H->vinv,
+                                          kReorthEta, 1, s)) return e;
+        if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 1,
+                                      H->partials, kRedBlocks, nullptr, s)) return e;
+        if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums2, s)) return e;
+        if (int e = launch_arnoldi_finish(j, nullptr, sums2, nullptr, H->gate, H->hcol, H->vinv,
+                                          kReorthEta, 2, s)) return e;
+        const long long passC = prof_mark();
+        if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 0,
+                                      H->partials, kRedBlocks, H->gate, s)) return e;
+        if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums3, s)) return e;
+        if (int e = launch_arnoldi_finish(j, nullptr, nullptr, sums3, H->gate, H->hcol,
+                                          H->vinv, kReorthEta, 3, s)) return e;
+        KKT_HIP(hipMemcpyAsync(H->host_hcol, H->hcol, (j + 3) * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+        KKT_HIP(hipStreamSynchronize(s));
+        const double* hc = H->host_hcol;
+        if (hc[j + 2] != 0.0) {
+          ++st.reorth;
+          prof_add_bytes(passC, (double)(nv + 2) * n3 * 8.0);   // the gated pass ran
         }
-        Hm[(size_t)i * R + j] = hc[i];
+        for (int i = 0; i <= j + 1; ++i) {
+          if (!std::isfinite(hc[i])) return bad("non-finite Hessenberg entry");
+          Hm[(size_t)i * R + j] = hc[i];
+        }
+        const double sub = Hm[(size_t)(j + 1) * R + j];
+        rotate_column(j);
+        alpha[j] = 1.0;
+        for (int i = 0; i < j; ++i) amat[(size_t)i * (R + 1) + j] = 0.0;
+        ++its;
+        m = j + 1;
+        est = std::fabs(gv[j + 1]) / fnorm;
+        if (std::fabs(gv[j + 1]) <= tol || its >= maxit || sub == 0.0) break;
+        continue;
       }
-      // apply previous rotations, then the new one
-      for (int i = 0; i < j; ++i) {
-        const double a = Hm[(size_t)i * R + j], b = Hm[(size_t)(i + 1) * R + j];
-        Hm[(size_t)i * R + j] = cs[i] * a + sn[i] * b;
-        Hm[(size_t)(i + 1) * R + j] = -sn[i] * a + cs[i] * b;
+      // ---- DCGS2: slot j holds the candidate of v_j, slot j+1 the product W ---------------
+      const int ns = 2 * j + 3;
+      if (int e = launch_dcgs_dots(n3, V, ldv, j, vj, w, H->partials, kRedBlocks, s)) return e;
+      if (int e = launch_reduce_partials(H->partials, kRedBlocks, ns, sums, s)) return e;
+      if (int e = launch_dcgs_finish(j, sums, H->vinv, H->ydev, rec, H->gate, 1, s)) return e;
+      if (int e = launch_dcgs_update(n3, V, ldv, j, H->ydev, H->gate, H->partials, kRedBlocks, s)) return e;
+      if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums + 100, s)) return e;
+      if (int e = launch_dcgs_finish(j, sums + 100, H->vinv, H->ydev, rec, H->gate, 2, s)) return e;
+      KKT_HIP(hipMemcpyAsync(H->host_hcol, rec, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
+      KKT_HIP(hipStreamSynchronize(s));
+      for (int i = 0; i < 2 * j + 5; ++i)
+        if (!std::isfinite(hrec[i])) return bad("non-finite Arnoldi coefficient");
+      const double al = hrec[0], nu = hrec[1], hjj = hrec[2 * j + 2], nu1 = hrec[2 * j + 3];
+      const bool brk = hrec[2 * j + 4] != 0.0;
+      ++st.reorth;
+      // close column j-1 with the reorthogonalisation of its candidate
+      if (j == 0) {
+        gv[0] = beta * al;
+      } else {
+        for (int i = 0; i < j; ++i) Hm[(size_t)i * R + (j - 1)] += nu * hrec[2 + i];
+        Hm[(size_t)j * R + (j - 1)] = nu * al;
+        rotate_column(j - 1);
+        est = std::fabs(gv[j]) / fnorm;
       }
-      const double a = Hm[(size_t)j * R + j], b = Hm[(size_t)(j + 1) * R + j];
-      const double rho = std::hypot(a, b);
-      cs[j] = rho == 0.0 ? 1.0 : a / rho;
-      sn[j] = rho == 0.0 ? 0.0 : b / rho;
-      Hm[(size_t)j * R + j] = rho;
-      Hm[(size_t)(j + 1) * R + j] = 0.0;
-      gv[j + 1] = -sn[j] * gv[j];
-      gv[j] = cs[j] * gv[j];
+      alpha[j] = al;
+      for (int i = 0; i < j; ++i) amat[(size_t)i * (R + 1) + j] = hrec[2 + i];
+      if (brk || (j > 0 && std::fabs(gv[j]) <= tol)) {
+        // the candidate lies in the span of v_0..v_{j-1}, or those columns already converged
+        m = j;
+        break;
+      }
+      // column j, projected once: b_i (i < j), hjj, and the norm of the next candidate
+      for (int i = 0; i < j; ++i) Hm[(size_t)i * R + j] = hrec[2 + j + i];
+      Hm[(size_t)j * R + j] = hjj;
+      Hm[(size_t)(j + 1) * R + j] = nu1;
       ++its;
+      std::vector<double> cand((size_t)j + 2);
+      for (int i = 0; i <= j + 1; ++i) cand[i] = Hm[(size_t)i * R + j];
+      const bool last = (j + 1 == R) || its >= maxit || nu1 == 0.0 || provisional(j, cand) <= tol;
+      if (!last) continue;
+      // close column j now: reorthogonalisation coefficients of the next candidate only
+      if (nu1 > 0.0) {
+        const int j1 = j + 1;
+        if (int e = launch_dcgs_dots(n3, V, ldv, j1, w, nullptr, H->partials, kRedBlocks, s)) return e;
+        if (int e = launch_reduce_partials(H->partials, kRedBlocks, 2 * j1 + 3, sums, s)) return e;
+        if (int e = launch_dcgs_finish(j1, sums, H->vinv, H->ydev, rec, H->gate, 3, s)) return e;
+        KKT_HIP(hipMemcpyAsync(H->host_hcol, rec, (2 * j1 + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
+        KKT_HIP(hipStreamSynchronize(s));
+        for (int i = 0; i < 2 + j1; ++i)
+          if (!std::isfinite(hrec[i])) return bad("non-finite Arnoldi coefficient");
+        for (int i = 0; i <= j; ++i) Hm[(size_t)i * R + j] += nu1 * hrec[2 + i];
+        Hm[(size_t)(j + 1) * R + j] = nu1 * hrec[0];
+      }
+      rotate_column(j);
       est = std::fabs(gv[j + 1]) / fnorm;
-      jend = j + 1;
-      breakdown = (b == 0.0);
-      if (std::fabs(gv[j + 1]) <= tol || its >= maxit || breakdown) break;
+      m = j + 1;
+      break;
     }
-    // x += Z y with y from the rotated triangular system
-    for (int i = jend - 1; i >= 0; --i) {
+    if (m == 0) return bad("Arnoldi breakdown on the first basis vector");
+    // x += Z y with y from the rotated triangular system of the m closed columns
+    for (int i = m - 1; i >= 0; --i) {
       double t = gv[i];
-      for (int m = i + 1; m < jend; ++m) t -= Hm[(size_t)i * R + m] * y[m];
+      for (int q = i + 1; q < m; ++q) t -= Hm[(size_t)i * R + q] * y[q];
       y[i] = t / Hm[(size_t)i * R + i];
     }
-    std::copy(y.begin(), y.begin() + jend, H->host_sums + 32);   // pinned staging slots
-    KKT_HIP(hipMemcpyAsync(H->ydev, H->host_sums + 32, jend * sizeof(double), hipMemcpyHostToDevice, s));
-    if (int e = launch_update_solution(g, V, ldv, Zw, g.P, jend, H->ydev, H->vinv, 1.0 / g.h,
-                                       1.0 / (g.omega * g.h), x, s)) return e;
-    (void)breakdown;
+    // z_j's u and z blocks are its candidate alpha_j v_j + sum_{i<j} a_ij v_i, scaled
+    for (int i = 0; i < m; ++i) {
+      double c = y[i] * alpha[i];
+      for (int q = i + 1; q < m; ++q) c += y[q] * amat[(size_t)i * (R + 1) + q];
+      yv[i] = c;
+      yw[i] = y[i];
+    }
+    if (m > 0) {
+      double* stage = H->host_sums + 32;   // pinned staging: R + m <= 62 doubles
+      std::copy(yv.begin(), yv.begin() + m, stage);
+      std::copy(yw.begin(), yw.begin() + m, stage + R);
+      KKT_HIP(hipMemcpyAsync(H->ydev + 64, stage, (size_t)(R + m) * sizeof(double), hipMemcpyHostToDevice, s));
+      if (int e = launch_update_solution(g, V, ldv, Zw, g.P, m, H->ydev + 64, H->ydev + 64 + R,
+                                         H->vinv, 1.0 / g.h, 1.0 / (g.omega * g.h), x, s)) return e;
+      KKT_HIP(hipStreamSynchronize(s));   // the staging buffer is reused by the next cycle
+    }
   }
 }
 

@@ -140,10 +140,17 @@ int launch_reduce_partials(const double* partials, int nblocks, int nsums, doubl
 int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const double* sums3,
                           int* gate, double* hcol, double* vinv, double eta, int stage,
                           hipStream_t s);
-// x_f += sum_i y[i] * fscale_f * vinv[i] * V_i,f for f = u, z; x_w += sum_i y[i] * Zw_i.
+// x_f += sum_i yv[i] * fscale_f * vinv[i] * V_i,f for f = u, z; x_w += sum_i yw[i] * Zw_i.
 int launch_update_solution(const Geom& g, const double* V, long long ldv, const double* Zw,
-                           long long ldz, int nv, const double* y, const double* vinv,
-                           double su, double sz, double* x, hipStream_t s);
+                           long long ldz, int nv, const double* yv, const double* yw,
+                           const double* vinv, double su, double sz, double* x, hipStream_t s);
+// DCGS2 Arnoldi (see krylov.hip): inner products, bookkeeping, combined update pass.
+int launch_dcgs_dots(long long n, const double* V, long long ldv, int j, const double* Vc,
+                     const double* W, double* partials, int nblocks, hipStream_t s);
+int launch_dcgs_finish(int j, const double* sums, double* vinv, double* coef, double* rec,
+                       int* gate, int stage, hipStream_t s);
+int launch_dcgs_update(long long n, double* V, long long ldv, int j, const double* coef,
+                       const int* gate, double* partials, int nblocks, hipStream_t s);
 int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
                         hipStream_t s);
 

@@ -144,6 +144,185 @@ k_update_dot(long long n, const double* __restrict__ V, long long ldv, int nv,
   block_sums<MAXV + 1>(out, ns, partials + (long long)blockIdx.x * ns);
 }
 
+// ---- delayed classical Gram-Schmidt with reorthogonalisation (DCGS2) -------------------
+// Arnoldi step j holds final basis vectors in slots 0..j-1, the once-orthogonalised
+// candidate of basis vector j in slot j and the new product W = K z_j in slot j+1.  One
+// pass forms every inner product the step needs,
+//     A_i = <V_i, Vc>, B_i = <V_i, W> (i < j), C = <Vc, Vc>, E = <Vc, W>, F = <W, W>,
+// and one pass applies them: the candidate is reorthogonalised into the final v_j and W is
+// projected once against v_0..v_j, becoming the next candidate.  So each step reads the basis
+// twice instead of three times (Swirydowicz et al. 2021; Bielich et al. 2022).
+template <int MAXV>
+__global__ void __launch_bounds__(kBlock)
+k_dcgs_dots(long long n, const double* __restrict__ V, long long ldv, int j,
+            const double* __restrict__ Vc, const double* __restrict__ W,
+            double* __restrict__ partials) {
+  constexpr int MAXS = 2 * MAXV + 3;
+  double acc[MAXS];
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i) acc[i] = 0.0;
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
+  const double2* __restrict__ c2 = reinterpret_cast<const double2*>(Vc);
+  const double2* __restrict__ w2 = reinterpret_cast<const double2*>(W);
+  const bool hasW = W != nullptr;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+    const double2 c = c2[e];
+    const double2 w = hasW ? w2[e] : double2{0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < j) {
+        const double2 v = V2[i * ld2 + e];
+        acc[i] += v.x * c.x + v.y * c.y;
+        acc[MAXV + i] += v.x * w.x + v.y * w.y;
+      }
+    acc[2 * MAXV] += c.x * c.x + c.y * c.y;
+    acc[2 * MAXV + 1] += c.x * w.x + c.y * w.y;
+    acc[2 * MAXV + 2] += w.x * w.x + w.y * w.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const double c = Vc[n - 1], w = hasW ? W[n - 1] : 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < j) {
+        const double v = V[i * ldv + n - 1];
+        acc[i] += v * c;
+        acc[MAXV + i] += v * w;
+      }
+    acc[2 * MAXV] += c * c;
+    acc[2 * MAXV + 1] += c * w;
+    acc[2 * MAXV + 2] += w * w;
+  }
+  // compact to [A_0..A_{j-1}, B_0..B_{j-1}, C, E, F]
+  const int ns = 2 * j + 3;
+  double out[MAXS];
+#pragma unroll
+  for (int i = 0; i < MAXS; ++i) {
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < MAXV; ++q) {
+      if (i == q && q < j) v = acc[q];
+      if (i == j + q && q < j) v = acc[MAXV + q];
+    }
+    if (i == 2 * j) v = acc[2 * MAXV];
+    if (i == 2 * j + 1) v = acc[2 * MAXV + 1];
+    if (i == 2 * j + 2) v = acc[2 * MAXV + 2];
+    out[i] = v;
+  }
+  block_sums<MAXS>(out, ns, partials + (long long)blockIdx.x * ns);
+}
+
+// coef = [cv, hjj, p_0..p_{j-1}, q_0..q_{j-1}]:
+//   slot j   <- v  = cv * Vc - sum_i p_i V_i
+//   slot j+1 <- W' = W - sum_i q_i V_i - hjj * v,  with partial sums of ||W'||^2.
+template <int MAXV>
+__global__ void __launch_bounds__(kBlock)
+k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __restrict__ coef,
+              const int* __restrict__ gate, double* __restrict__ partials) {
+  if (gate && *gate == 0) return;
+  const double cv = coef[0], hjj = coef[1];
+  double p[MAXV], q[MAXV];
+#pragma unroll
+  for (int i = 0; i < MAXV; ++i) {
+    p[i] = i < j ? coef[2 + i] : 0.0;
+    q[i] = i < j ? coef[2 + j + i] : 0.0;
+  }
+  const long long n2 = n >> 1, ld2 = ldv >> 1;
+  double2* V2 = reinterpret_cast<double2*>(V);
+  double2* c2 = V2 + (long long)j * ld2;
+  double2* w2 = c2 + ld2;
+  double acc = 0.0;
+  const long long stride = (long long)gridDim.x * kBlock;
+  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+    const double2 c = c2[e];
+    double2 w = w2[e];
+    double2 v = {cv * c.x, cv * c.y};
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < j) {
+        const double2 b = V2[i * ld2 + e];
+        v.x -= p[i] * b.x;
+        v.y -= p[i] * b.y;
+        w.x -= q[i] * b.x;
+        w.y -= q[i] * b.y;
+      }
+    w.x -= hjj * v.x;
+    w.y -= hjj * v.y;
+    c2[e] = v;
+    w2[e] = w;
+    acc += w.x * w.x + w.y * w.y;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    double* c = V + (long long)j * ldv;
+    double* w = c + ldv;
+    double v = cv * c[n - 1], x = w[n - 1];
+#pragma unroll
+    for (int i = 0; i < MAXV; ++i)
+      if (i < j) {
+        const double b = V[i * ldv + n - 1];
+        v -= p[i] * b;
+        x -= q[i] * b;
+      }
+    x -= hjj * v;
+    c[n - 1] = v;
+    w[n - 1] = x;
+    acc += x * x;
+  }
+  double out[1] = {acc};
+  block_sums<1>(out, 1, partials + blockIdx.x);
+}
+
+// One-thread bookkeeping of a DCGS2 step.  vinv[i] scales slot i (1 for final vectors).
+// rec (host-visible) = [alpha, nu, a_0..a_{j-1}, b_0..b_{j-1}, hjj, nu_next, breakdown]
+//   stage 1 (sums of a full step):   reorthogonalisation of the candidate, projection of W,
+//                                    update coefficients; gate = 0 on breakdown
+//   stage 2 (sum of ||W'||^2):       normalisation scales of slots j and j+1
+//   stage 3 (sums without W):        reorthogonalisation coefficients only (closing a column)
+__global__ void k_dcgs_finish(int j, const double* __restrict__ sums, double* __restrict__ vinv,
+                              double* __restrict__ coef, double* __restrict__ rec,
+                              int* __restrict__ gate, int stage) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* a = rec + 2;
+  double* b = rec + 2 + j;
+  if (stage == 1 || stage == 3) {
+    const double sc = vinv[j];
+    double sa = 0.0;
+    for (int i = 0; i < j; ++i) {
+      a[i] = vinv[i] * sc * sums[i];
+      sa += a[i] * a[i];
+    }
+    const double c = sc * sc * sums[2 * j];
+    const double al2 = c - sa;
+    const bool brk = !(al2 > 1e-24 * c) || !(c > 0.0);
+    const double alpha = brk ? 0.0 : sqrt(al2);
+    rec[0] = alpha;
+    rec[1] = sc > 0.0 ? 1.0 / sc : 0.0;
+    rec[2 * j + 4] = brk ? 1.0 : 0.0;
+    if (stage == 3) return;
+    double ab = 0.0;
+    for (int i = 0; i < j; ++i) {
+      b[i] = vinv[i] * sums[j + i];
+      ab += a[i] * b[i];
+    }
+    const double e = sc * sums[2 * j + 1];
+    const double hjj = brk ? 0.0 : (e - ab) / alpha;
+    rec[2 * j + 2] = hjj;
+    coef[0] = brk ? 0.0 : sc / alpha;
+    coef[1] = hjj;
+    for (int i = 0; i < j; ++i) {
+      coef[2 + i] = brk ? 0.0 : a[i] * vinv[i] / alpha;
+      coef[2 + j + i] = b[i] * vinv[i];
+    }
+    *gate = brk ? 0 : 1;
+  } else if (*gate) {
+    const double nu = sqrt(sums[0]);
+    rec[2 * j + 3] = nu;
+    vinv[j] = 1.0;
+    vinv[j + 1] = nu > 0.0 ? 1.0 / nu : 0.0;
+  }
+}
+
 // out[i] = sum over blocks of partials[b*nsums + i], in block order.
 __global__ void __launch_bounds__(kBlock)
 k_reduce_partials(const double* __restrict__ partials, int nblocks, int nsums,
@@ -208,11 +387,13 @@ __global__ void k_arnoldi_finish(int j, const double* sums1, const double* sums2
   }
 }
 
+// x_u += su * sum_i yv[i] vinv[i] V_i,u;  x_z += sz * (same with V_i,z);  x_w += sum_i yw[i] Zw_i
+// (yv and yw are the coefficients of the basis vectors and of the stored w-blocks).
 __global__ void __launch_bounds__(kBlock)
 k_update_solution(Geom g, const double* __restrict__ V, long long ldv,
                   const double* __restrict__ Zw, long long ldz, int nv,
-                  const double* __restrict__ y, const double* __restrict__ vinv, double su,
-                  double sz, double* __restrict__ x) {
+                  const double* __restrict__ yv, const double* __restrict__ yw,
+                  const double* __restrict__ vinv, double su, double sz, double* __restrict__ x) {
   const long long n3 = 3 * g.P;
   const long long stride = (long long)gridDim.x * kBlock;
   for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n3; e += stride) {
@@ -220,10 +401,10 @@ k_update_solution(Geom g, const double* __restrict__ V, long long ldv,
     double acc = 0.0;
     if (f < 2) {
       const double sf = f == 0 ? su : sz;
-      for (int i = 0; i < nv; ++i) acc += (y[i] * vinv[i] * sf) * V[i * ldv + e];
+      for (int i = 0; i < nv; ++i) acc += (yv[i] * vinv[i] * sf) * V[i * ldv + e];
     } else {
       const long long off = e - 2 * g.P;
-      for (int i = 0; i < nv; ++i) acc += y[i] * Zw[i * ldz + off];
+      for (int i = 0; i < nv; ++i) acc += yw[i] * Zw[i * ldz + off];
     }
     x[e] += acc;
   }
@@ -311,15 +492,62 @@ int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const
   return 0;
 }
 
+int launch_dcgs_dots(long long n, const double* V, long long ldv, int j, const double* Vc,
+                     const double* W, double* partials, int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks), block(kBlock);
+  prof_begin(KKTDD_K_ARNOLDI, s);
+  if (j <= 8)
+    hipLaunchKernelGGL((k_dcgs_dots<8>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
+  else if (j <= 16)
+    hipLaunchKernelGGL((k_dcgs_dots<16>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
+  else if (j <= 24)
+    hipLaunchKernelGGL((k_dcgs_dots<24>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
+  else if (j <= 32)
+    hipLaunchKernelGGL((k_dcgs_dots<32>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
+  else
+    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + (W ? 2 : 1)) * n, 0.0);
+  return 0;
+}
+
+int launch_dcgs_update(long long n, double* V, long long ldv, int j, const double* coef,
+                       const int* gate, double* partials, int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks), block(kBlock);
+  prof_begin(KKTDD_K_ARNOLDI, s);
+  if (j <= 8)
+    hipLaunchKernelGGL((k_dcgs_update<8>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 16)
+    hipLaunchKernelGGL((k_dcgs_update<16>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 24)
+    hipLaunchKernelGGL((k_dcgs_update<24>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 32)
+    hipLaunchKernelGGL((k_dcgs_update<32>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else
+    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + 4) * n, 0.0);
+  return 0;
+}
+
+int launch_dcgs_finish(int j, const double* sums, double* vinv, double* coef, double* rec,
+                       int* gate, int stage, hipStream_t s) {
+  prof_begin(KKTDD_K_ARNOLDI, s);
+  hipLaunchKernelGGL(k_dcgs_finish, dim3(1), dim3(64), 0, s, j, sums, vinv, coef, rec, gate, stage);
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_ARNOLDI, s, 0.0, 0.0);
+  return 0;
+}
+
 int launch_update_solution(const Geom& g, const double* V, long long ldv, const double* Zw,
-                           long long ldz, int nv, const double* y, const double* vinv,
-                           double su, double sz, double* x, hipStream_t s) {
+                           long long ldz, int nv, const double* yv, const double* yw,
+                           const double* vinv, double su, double sz, double* x, hipStream_t s) {
   const long long n3 = 3 * g.P;
   long long nb = (n3 + kBlock - 1) / kBlock;
   if (nb > 8192) nb = 8192;
   prof_begin(KKTDD_K_OTHER, s);
   hipLaunchKernelGGL(k_update_solution, dim3((unsigned)nb), dim3(kBlock), 0, s, g, V, ldv, Zw, ldz,
-                     nv, y, vinv, su, sz, x);
+                     nv, yv, yw, vinv, su, sz, x);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_OTHER, s, 8.0 * g.P * (2.0 * nv + nv + 6.0), 0.0);
   return 0;
