@@ -40,6 +40,10 @@
 extern "C" {
 #endif
 
+/* Longest Arnoldi cycle fgmres_solve takes: enough to run the unrestarted GMRES of the
+ * experiments of Sec. 4 (at most 420 iterations) as a single cycle. */
+#define KKTDD_MAX_RESTART 1024
+
 enum kktdd_status {
   KKTDD_OK = 0,
   KKTDD_NOT_CONVERGED = 1, /* maxit reached; x holds the last iterate                        */
@@ -144,7 +148,9 @@ int kkt_spatial_solve(kktdd_handle* h, const double* b, double* x, int32_t nslic
  * initial guess on entry and the iterate on exit.  Stops at the first Arnoldi step whose
  * rotated residual estimate is <= rtol*||f||, confirmed by the true residual (a new cycle
  * starts otherwise), or after maxit Arnoldi steps (KKTDD_NOT_CONVERGED).  f = 0 returns x = 0.
- * Allocates the Krylov basis on first use of a restart length.  `stats` may be NULL. */
+ * 1 <= restart <= KKTDD_MAX_RESTART (31 with the KKTDD_ARNOLDI=cgs passes); the basis of
+ * restart+1 vectors and restart stored w-blocks is allocated on first use of a longer cycle
+ * (kkt_memory_plan gives its size).  `stats` may be NULL. */
 int fgmres_solve(kktdd_handle* h, const double* f, double* x, int32_t restart, int32_t maxit,
                  double rtol, kktdd_stats* stats);
 

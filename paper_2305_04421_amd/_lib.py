@@ -19,6 +19,8 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3, "bf16x
 # enum kktdd_sweep
 SWEEP_STEP, SWEEP_MODAL = 0, 1
 SWEEPS = {"step": SWEEP_STEP, "modal": SWEEP_MODAL}
+# longest Arnoldi cycle of fgmres_solve
+MAX_RESTART = 1024
 
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_rhs",
             "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",

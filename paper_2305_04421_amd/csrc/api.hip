@@ -29,8 +29,9 @@ bool arnoldi_dcgs2() {
   }();
   return v;
 }
-constexpr int kRedBlocks = 1024;   // blocks of the two-stage reductions
-constexpr int kMaxSums = 72;       // per-block partial sums of one reduction (2*31 + 3 <= 72)
+constexpr int kRedBlocks = 1024;   // most blocks of a two-stage reduction
+constexpr int kFieldSums = 3;      // per-block partial sums of a field reduction
+constexpr int kMaxCgsRestart = 31; // the CGS passes keep one accumulator per basis vector
 constexpr double kReorthEta = 0.70710678118654752;  // 1/sqrt(2)
 }  // namespace
 
@@ -122,11 +123,12 @@ struct kktdd_handle {
   // reductions
   double *partials = nullptr, *sums = nullptr;
   double* host_sums = nullptr;                 // pinned
-  // Krylov
+  // Krylov basis and its bookkeeping, sized for restart length R (see krylov_small)
   int R = 0;
-  double *V = nullptr, *Zw = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
+  double *V = nullptr, *Zw = nullptr;
+  double *kpart = nullptr, *ksums = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
   int* gate = nullptr;
-  double* host_hcol = nullptr;                 // pinned
+  double* host_hcol = nullptr;                 // pinned, KrylovSmall(R).host doubles
   Prof prof;
 
   uint16_t *SxBF = nullptr, *SyBF = nullptr;  // bfloat16 parts (3 per matrix) of S_x, S_y
@@ -229,6 +231,28 @@ Geom make_geom(const kktdd_problem& p) {
 // starts 512-byte aligned (the Arnoldi kernels stream them with 16-byte loads).
 long long krylov_ld(const Geom& g) { return (3 * g.P + 63) / 64 * 64; }
 
+// Blocks of the Arnoldi reductions: one element pair per thread at most, kRedBlocks at most.
+int krylov_blocks(const Geom& g) {
+  const long long pairs = (3 * g.P + 1) / 2;
+  const long long b = (pairs + 255) / 256;
+  return (int)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
+}
+
+// Small Krylov buffers for restart length R (doubles):
+//   part  per-block partial sums, blocks x (2R+3)
+//   sums  reduced sums: DCGS2 [0, 2R+3) plus the norm slot at 2R+4; CGS three runs of R+2
+//   rec   Arnoldi record read back by the host (DCGS2 2j+5, CGS 2(j+3)+1 doubles, j < R)
+//   vinv  basis scales, R+2
+//   ydev  update coefficients [0, 2R+2), then the solution coefficients yv, yw at 2R+4
+//   host  pinned: the record, then the staged yv, yw at 2R+8
+struct KrylovSmall {
+  size_t part, sums, rec, vinv, ydev, host;
+  explicit KrylovSmall(int R)
+      : part((size_t)kRedBlocks * (2 * R + 3)), sums(3 * (size_t)R + 8), rec(2 * (size_t)R + 8),
+        vinv((size_t)R + 2), ydev(4 * (size_t)R + 4), host(4 * (size_t)R + 8) {}
+  size_t device_bytes() const { return (part + sums + rec + vinv + ydev) * 8 + 256; }
+};
+
 struct Plan {
   size_t tables, sweeps, coarse, krylov;
   size_t total() const { return tables + sweeps + coarse + krylov; }
@@ -266,8 +290,10 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
     p.coarse = (size_t)g.nc * MM * 8 * 2 + (size_t)g.nxy * g.nc * (hb + 1) * 8;
     if (physical_coarse(g, precision, sweep)) p.coarse += (size_t)g.nc * g.nxy * 8 * 4;
   }
-  p.coarse += (size_t)kRedBlocks * kMaxSums * 8 + 128 * 8;
-  if (R > 0) p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 + 4096;
+  p.coarse += (size_t)kRedBlocks * kFieldSums * 8 + 128 * 8;
+  if (R > 0)
+    p.krylov = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 +
+               KrylovSmall(R).device_bytes();
   return p;
 }
 
@@ -473,7 +499,7 @@ int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double*
 // squared norms of the three fields of a KKT vector, to the host (synchronises)
 int field_sumsq(kktdd_handle* H, const double* r, double out[3]) {
   if (int e = launch_sumsq_blocks(H->g, r, H->partials, kRedBlocks, H->stream)) return e;
-  if (int e = launch_reduce_partials(H->partials, kRedBlocks, 3, H->sums, H->stream)) return e;
+  if (int e = launch_reduce_partials(H->partials, kRedBlocks, kFieldSums, H->sums, H->stream)) return e;
   KKT_HIP(hipMemcpyAsync(H->host_sums, H->sums, 3 * sizeof(double), hipMemcpyDeviceToHost, H->stream));
   KKT_HIP(hipStreamSynchronize(H->stream));
   for (int i = 0; i < 3; ++i) out[i] = H->host_sums[i];
@@ -493,13 +519,20 @@ int ensure_krylov(kktdd_handle* H, int R) {
         break;
       }
   };
-  release(H->V);
-  release(H->Zw);
-  H->V = H->Zw = nullptr;
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  for (void* p : {(void*)H->V, (void*)H->Zw, (void*)H->kpart, (void*)H->ksums, (void*)H->hcol,
+                  (void*)H->vinv, (void*)H->ydev, (void*)H->gate})
+    release(p);
+  H->V = H->Zw = H->kpart = H->ksums = H->hcol = H->vinv = H->ydev = nullptr;
+  H->gate = nullptr;
+  if (H->host_hcol) (void)hipHostFree(H->host_hcol);
+  H->host_hcol = nullptr;
   H->R = 0;
+  const KrylovSmall ks(R);
   size_t free_b = 0, total_b = 0;
   KKT_HIP(hipMemGetInfo(&free_b, &total_b));
-  const size_t need = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8;
+  const size_t need = ((size_t)(R + 1) * (size_t)krylov_ld(g) + (size_t)R * (size_t)g.P) * 8 +
+                      ks.device_bytes();
   if (need > free_b) {
     char buf[200];
     std::snprintf(buf, sizeof buf, "Krylov basis for restart %d needs %zu bytes, %zu free", R, need, free_b);
@@ -507,6 +540,17 @@ int ensure_krylov(kktdd_handle* H, int R) {
   }
   if (int e = dalloc(H, &H->V, (size_t)(R + 1) * (size_t)krylov_ld(g))) return e;
   if (int e = dalloc(H, &H->Zw, (size_t)R * g.P)) return e;
+  if (int e = dalloc(H, &H->kpart, ks.part)) return e;
+  if (int e = dalloc(H, &H->ksums, ks.sums)) return e;
+  if (int e = dalloc(H, &H->hcol, ks.rec)) return e;
+  if (int e = dalloc(H, &H->vinv, ks.vinv)) return e;
+  if (int e = dalloc(H, &H->ydev, ks.ydev)) return e;
+  if (int e = dalloc(H, &H->gate, 1)) return e;
+  if (hipHostMalloc((void**)&H->host_hcol, ks.host * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    H->host_hcol = nullptr;
+    return set_error(KKTDD_EHIP, "hipHostMalloc failed");
+  }
   H->R = R;
   return 0;
 }
@@ -596,7 +640,7 @@ int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) 
       return fail(set_error(KKTDD_EHIP, "hipMemsetAsync failed"));
     }
   }
-  if (int e = dalloc(H, &H->partials, (size_t)kRedBlocks * kMaxSums)) return fail(e);
+  if (int e = dalloc(H, &H->partials, (size_t)kRedBlocks * kFieldSums)) return fail(e);
   if (int e = dalloc(H, &H->sums, 128)) return fail(e);
   if (hipHostMalloc((void**)&H->host_sums, 128 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
@@ -703,24 +747,17 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   ProfScope ps(H);
   if (!H || !f || !x) return set_error(KKTDD_EINVAL, "NULL argument");
   if (f == x) return set_error(KKTDD_EINVAL, "f and x must not alias");
-  if (restart < 1 || restart > 31 || maxit < 0 || !(rtol > 0.0))
-    return set_error(KKTDD_EINVAL, "need 1 <= restart <= 31, maxit >= 0, rtol > 0");
+  const bool dcgs = arnoldi_dcgs2();
+  if (restart < 1 || restart > KKTDD_MAX_RESTART || maxit < 0 || !(rtol > 0.0))
+    return set_error(KKTDD_EINVAL, "need 1 <= restart <= KKTDD_MAX_RESTART, maxit >= 0, rtol > 0");
+  if (!dcgs && restart > kMaxCgsRestart)
+    return set_error(KKTDD_EINVAL, "the CGS Arnoldi passes take restart <= 31");
   kktdd_stats st{};
   const Geom& g = H->g;
   hipStream_t s = H->stream;
   const long long n3 = 3 * g.P;
+  const int nred = krylov_blocks(g);
   if (int e = ensure_krylov(H, restart)) return e;
-  if (!H->hcol) {
-    if (int e = dalloc(H, &H->hcol, 3 * 40)) return e;
-    if (int e = dalloc(H, &H->vinv, 40)) return e;
-    if (int e = dalloc(H, &H->ydev, 160)) return e;
-    if (int e = dalloc(H, &H->gate, 1)) return e;
-    if (hipHostMalloc((void**)&H->host_hcol, 3 * 40 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      H->host_hcol = nullptr;
-      return set_error(KKTDD_EHIP, "hipHostMalloc failed");
-    }
-  }
   double fb[3];
   if (int e = field_sumsq(H, f, fb)) return e;
   const double fnorm = std::sqrt(fb[0] + fb[1] + fb[2]);
@@ -750,7 +787,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   const long long ldv = krylov_ld(g);
   double* V = H->V;
   double* Zw = H->Zw;
-  const bool dcgs = arnoldi_dcgs2();
+  double* part = H->kpart;
   // Hessenberg (R+1) x R row-major, Givens rotations, rotated right-hand side
   std::vector<double> Hm((size_t)(R + 1) * R), cs(R), sn(R), gv(R + 1), y(R), yv(R), yw(R);
   // DCGS2: alpha[j] and amat[i*(R+1)+j] = coefficients of the candidate of step j in the
@@ -818,7 +855,8 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
     std::fill(gv.begin(), gv.end(), 0.0);
     gv[0] = beta;
     int m = 0;   // columns of this cycle that enter the solution
-    double* sums = H->sums;
+    double* sums = H->ksums;
+    double* norm_slot = H->ksums + 2 * R + 4;
     double* rec = H->hcol;
     const double* hrec = H->host_hcol;
     for (int j = 0; j < R; ++j) {
@@ -833,22 +871,22 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       if (!dcgs) {
         // ---- classical Gram-Schmidt with selective reorthogonalisation ------------------
         const int nv = j + 1;
-        double* sums1 = H->sums;
-        double* sums2 = H->sums + 40;
-        double* sums3 = H->sums + 80;
-        if (int e = launch_multidot(n3, V, ldv, nv, H->vinv, w, 1, H->partials, kRedBlocks, s)) return e;
-        if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums1, s)) return e;
+        double* sums1 = H->ksums;
+        double* sums2 = H->ksums + (R + 2);
+        double* sums3 = H->ksums + 2 * (R + 2);
+        if (int e = launch_multidot(n3, V, ldv, nv, H->vinv, w, 1, part, nred, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, nv + 1, sums1, s)) return e;
         if (int e = launch_arnoldi_finish(j, sums1, nullptr, nullptr, H->gate, H->hcol, H->vinv,
                                           kReorthEta, 1, s)) return e;
         if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 1,
-                                      H->partials, kRedBlocks, nullptr, s)) return e;
-        if (int e = launch_reduce_partials(H->partials, kRedBlocks, nv + 1, sums2, s)) return e;
+                                      part, nred, nullptr, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, nv + 1, sums2, s)) return e;
         if (int e = launch_arnoldi_finish(j, nullptr, sums2, nullptr, H->gate, H->hcol, H->vinv,
                                           kReorthEta, 2, s)) return e;
         const long long passC = prof_mark();
         if (int e = launch_update_dot(n3, V, ldv, nv, H->vinv, H->hcol + (j + 3), w, w, 0,
-                                      H->partials, kRedBlocks, H->gate, s)) return e;
-        if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums3, s)) return e;
+                                      part, nred, H->gate, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, 1, sums3, s)) return e;
         if (int e = launch_arnoldi_finish(j, nullptr, nullptr, sums3, H->gate, H->hcol,
                                           H->vinv, kReorthEta, 3, s)) return e;
         KKT_HIP(hipMemcpyAsync(H->host_hcol, H->hcol, (j + 3) * sizeof(double),
@@ -875,12 +913,12 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       }
       // ---- DCGS2: slot j holds the candidate of v_j, slot j+1 the product W ---------------
       const int ns = 2 * j + 3;
-      if (int e = launch_dcgs_dots(n3, V, ldv, j, vj, w, H->partials, kRedBlocks, s)) return e;
-      if (int e = launch_reduce_partials(H->partials, kRedBlocks, ns, sums, s)) return e;
+      if (int e = launch_dcgs_dots(n3, V, ldv, j, vj, w, part, nred, s)) return e;
+      if (int e = launch_reduce_partials(part, nred, ns, sums, s)) return e;
       if (int e = launch_dcgs_finish(j, sums, H->vinv, H->ydev, rec, H->gate, 1, s)) return e;
-      if (int e = launch_dcgs_update(n3, V, ldv, j, H->ydev, H->gate, H->partials, kRedBlocks, s)) return e;
-      if (int e = launch_reduce_partials(H->partials, kRedBlocks, 1, sums + 100, s)) return e;
-      if (int e = launch_dcgs_finish(j, sums + 100, H->vinv, H->ydev, rec, H->gate, 2, s)) return e;
+      if (int e = launch_dcgs_update(n3, V, ldv, j, H->ydev, H->gate, part, nred, s)) return e;
+      if (int e = launch_reduce_partials(part, nred, 1, norm_slot, s)) return e;
+      if (int e = launch_dcgs_finish(j, norm_slot, H->vinv, H->ydev, rec, H->gate, 2, s)) return e;
       KKT_HIP(hipMemcpyAsync(H->host_hcol, rec, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
       KKT_HIP(hipStreamSynchronize(s));
       for (int i = 0; i < 2 * j + 5; ++i)
@@ -916,8 +954,8 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       // close column j now: reorthogonalisation coefficients of the next candidate only
       if (nu1 > 0.0) {
         const int j1 = j + 1;
-        if (int e = launch_dcgs_dots(n3, V, ldv, j1, w, nullptr, H->partials, kRedBlocks, s)) return e;
-        if (int e = launch_reduce_partials(H->partials, kRedBlocks, 2 * j1 + 3, sums, s)) return e;
+        if (int e = launch_dcgs_dots(n3, V, ldv, j1, w, nullptr, part, nred, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, 2 * j1 + 3, sums, s)) return e;
         if (int e = launch_dcgs_finish(j1, sums, H->vinv, H->ydev, rec, H->gate, 3, s)) return e;
         KKT_HIP(hipMemcpyAsync(H->host_hcol, rec, (2 * j1 + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
         KKT_HIP(hipStreamSynchronize(s));
@@ -946,11 +984,12 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       yw[i] = y[i];
     }
     if (m > 0) {
-      double* stage = H->host_sums + 32;   // pinned staging: R + m <= 62 doubles
+      double* stage = H->host_hcol + 2 * R + 8;   // pinned staging of yv, yw (2R doubles)
+      double* ystage = H->ydev + 2 * R + 4;
       std::copy(yv.begin(), yv.begin() + m, stage);
       std::copy(yw.begin(), yw.begin() + m, stage + R);
-      KKT_HIP(hipMemcpyAsync(H->ydev + 64, stage, (size_t)(R + m) * sizeof(double), hipMemcpyHostToDevice, s));
-      if (int e = launch_update_solution(g, V, ldv, Zw, g.P, m, H->ydev + 64, H->ydev + 64 + R,
+      KKT_HIP(hipMemcpyAsync(ystage, stage, (size_t)(R + m) * sizeof(double), hipMemcpyHostToDevice, s));
+      if (int e = launch_update_solution(g, V, ldv, Zw, g.P, m, ystage, ystage + R,
                                          H->vinv, 1.0 / g.h, 1.0 / (g.omega * g.h), x, s)) return e;
       KKT_HIP(hipStreamSynchronize(s));   // the staging buffer is reused by the next cycle
     }

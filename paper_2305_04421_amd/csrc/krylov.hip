@@ -152,82 +152,87 @@ k_update_dot(long long n, const double* __restrict__ V, long long ldv, int nv,
 // and one pass applies them: the candidate is reorthogonalised into the final v_j and W is
 // projected once against v_0..v_j, becoming the next candidate.  So each step reads the basis
 // twice instead of three times (Swirydowicz et al. 2021; Bielich et al. 2022).
-template <int MAXV>
+// Inner products of a DCGS2 step for any j: the basis is processed in chunks of 32 vectors
+// (register accumulators), each chunk re-streaming the candidate and W.  Per-block partial
+// sums are laid out as [A_0..A_{j-1}, B_0..B_{j-1}, C, E, F].
+constexpr int kChunk = 32;
+
 __global__ void __launch_bounds__(kBlock)
 k_dcgs_dots(long long n, const double* __restrict__ V, long long ldv, int j,
             const double* __restrict__ Vc, const double* __restrict__ W,
             double* __restrict__ partials) {
-  constexpr int MAXS = 2 * MAXV + 3;
-  double acc[MAXS];
-#pragma unroll
-  for (int i = 0; i < MAXS; ++i) acc[i] = 0.0;
+  const int ns = 2 * j + 3;
   const long long n2 = n >> 1, ld2 = ldv >> 1;
   const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
   const double2* __restrict__ c2 = reinterpret_cast<const double2*>(Vc);
   const double2* __restrict__ w2 = reinterpret_cast<const double2*>(W);
   const bool hasW = W != nullptr;
   const long long stride = (long long)gridDim.x * kBlock;
-  for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
-    const double2 c = c2[e];
-    const double2 w = hasW ? w2[e] : double2{0.0, 0.0};
+  const bool tail = (n & 1) && blockIdx.x == 0 && threadIdx.x == 0;
+  const int nchunks = j == 0 ? 1 : (j + kChunk - 1) / kChunk;
+  for (int c = 0; c < nchunks; ++c) {
+    const int i0 = c * kChunk;
+    const int cnt = j - i0 < kChunk ? j - i0 : kChunk;   // may be <= 0 when j == 0
+    double acc[2 * kChunk + 3];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < j) {
-        const double2 v = V2[i * ld2 + e];
-        acc[i] += v.x * c.x + v.y * c.y;
-        acc[MAXV + i] += v.x * w.x + v.y * w.y;
+    for (int i = 0; i < 2 * kChunk + 3; ++i) acc[i] = 0.0;
+    const bool first = c == 0;
+    for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
+      const double2 cv = c2[e];
+      const double2 w = hasW ? w2[e] : double2{0.0, 0.0};
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i)
+        if (i < cnt) {
+          const double2 v = V2[(long long)(i0 + i) * ld2 + e];
+          acc[i] += v.x * cv.x + v.y * cv.y;
+          acc[kChunk + i] += v.x * w.x + v.y * w.y;
+        }
+      if (first) {
+        acc[2 * kChunk] += cv.x * cv.x + cv.y * cv.y;
+        acc[2 * kChunk + 1] += cv.x * w.x + cv.y * w.y;
+        acc[2 * kChunk + 2] += w.x * w.x + w.y * w.y;
       }
-    acc[2 * MAXV] += c.x * c.x + c.y * c.y;
-    acc[2 * MAXV + 1] += c.x * w.x + c.y * w.y;
-    acc[2 * MAXV + 2] += w.x * w.x + w.y * w.y;
-  }
-  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
-    const double c = Vc[n - 1], w = hasW ? W[n - 1] : 0.0;
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < j) {
-        const double v = V[i * ldv + n - 1];
-        acc[i] += v * c;
-        acc[MAXV + i] += v * w;
-      }
-    acc[2 * MAXV] += c * c;
-    acc[2 * MAXV + 1] += c * w;
-    acc[2 * MAXV + 2] += w * w;
-  }
-  // compact to [A_0..A_{j-1}, B_0..B_{j-1}, C, E, F]
-  const int ns = 2 * j + 3;
-  double out[MAXS];
-#pragma unroll
-  for (int i = 0; i < MAXS; ++i) {
-    double v = 0.0;
-#pragma unroll
-    for (int q = 0; q < MAXV; ++q) {
-      if (i == q && q < j) v = acc[q];
-      if (i == j + q && q < j) v = acc[MAXV + q];
     }
-    if (i == 2 * j) v = acc[2 * MAXV];
-    if (i == 2 * j + 1) v = acc[2 * MAXV + 1];
-    if (i == 2 * j + 2) v = acc[2 * MAXV + 2];
-    out[i] = v;
+    if (tail) {
+      const double cv = Vc[n - 1], w = hasW ? W[n - 1] : 0.0;
+#pragma unroll
+      for (int i = 0; i < kChunk; ++i)
+        if (i < cnt) {
+          const double v = V[(long long)(i0 + i) * ldv + n - 1];
+          acc[i] += v * cv;
+          acc[kChunk + i] += v * w;
+        }
+      if (first) {
+        acc[2 * kChunk] += cv * cv;
+        acc[2 * kChunk + 1] += cv * w;
+        acc[2 * kChunk + 2] += w * w;
+      }
+    }
+    double* out = partials + (long long)blockIdx.x * ns;
+    if (cnt > 0) {
+      block_sums<kChunk>(*reinterpret_cast<double(*)[kChunk]>(acc), cnt, out + i0);
+      __syncthreads();
+      block_sums<kChunk>(*reinterpret_cast<double(*)[kChunk]>(acc + kChunk), cnt, out + j + i0);
+      __syncthreads();
+    }
+    if (first) {
+      block_sums<3>(*reinterpret_cast<double(*)[3]>(acc + 2 * kChunk), 3, out + 2 * j);
+      __syncthreads();
+    }
   }
-  block_sums<MAXS>(out, ns, partials + (long long)blockIdx.x * ns);
 }
 
 // coef = [cv, hjj, p_0..p_{j-1}, q_0..q_{j-1}]:
 //   slot j   <- v  = cv * Vc - sum_i p_i V_i
 //   slot j+1 <- W' = W - sum_i q_i V_i - hjj * v,  with partial sums of ||W'||^2.
-template <int MAXV>
+// The coefficients are wave-uniform, so they are read through the scalar cache.
 __global__ void __launch_bounds__(kBlock)
 k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __restrict__ coef,
               const int* __restrict__ gate, double* __restrict__ partials) {
   if (gate && *gate == 0) return;
   const double cv = coef[0], hjj = coef[1];
-  double p[MAXV], q[MAXV];
-#pragma unroll
-  for (int i = 0; i < MAXV; ++i) {
-    p[i] = i < j ? coef[2 + i] : 0.0;
-    q[i] = i < j ? coef[2 + j + i] : 0.0;
-  }
+  const double* p = coef + 2;
+  const double* q = coef + 2 + j;
   const long long n2 = n >> 1, ld2 = ldv >> 1;
   double2* V2 = reinterpret_cast<double2*>(V);
   double2* c2 = V2 + (long long)j * ld2;
@@ -238,15 +243,26 @@ k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __rest
     const double2 c = c2[e];
     double2 w = w2[e];
     double2 v = {cv * c.x, cv * c.y};
+    int i = 0;
+    for (; i + 4 <= j; i += 4) {
+      double2 b[4];
 #pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < j) {
-        const double2 b = V2[i * ld2 + e];
-        v.x -= p[i] * b.x;
-        v.y -= p[i] * b.y;
-        w.x -= q[i] * b.x;
-        w.y -= q[i] * b.y;
+      for (int u = 0; u < 4; ++u) b[u] = V2[(long long)(i + u) * ld2 + e];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v.x -= p[i + u] * b[u].x;
+        v.y -= p[i + u] * b[u].y;
+        w.x -= q[i + u] * b[u].x;
+        w.y -= q[i + u] * b[u].y;
       }
+    }
+    for (; i < j; ++i) {
+      const double2 b = V2[(long long)i * ld2 + e];
+      v.x -= p[i] * b.x;
+      v.y -= p[i] * b.y;
+      w.x -= q[i] * b.x;
+      w.y -= q[i] * b.y;
+    }
     w.x -= hjj * v.x;
     w.y -= hjj * v.y;
     c2[e] = v;
@@ -257,13 +273,11 @@ k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __rest
     double* c = V + (long long)j * ldv;
     double* w = c + ldv;
     double v = cv * c[n - 1], x = w[n - 1];
-#pragma unroll
-    for (int i = 0; i < MAXV; ++i)
-      if (i < j) {
-        const double b = V[i * ldv + n - 1];
-        v -= p[i] * b;
-        x -= q[i] * b;
-      }
+    for (int i = 0; i < j; ++i) {
+      const double b = V[(long long)i * ldv + n - 1];
+      v -= p[i] * b;
+      x -= q[i] * b;
+    }
     x -= hjj * v;
     c[n - 1] = v;
     w[n - 1] = x;
@@ -323,23 +337,20 @@ __global__ void k_dcgs_finish(int j, const double* __restrict__ sums, double* __
   }
 }
 
-// out[i] = sum over blocks of partials[b*nsums + i], in block order.
+// out[i] = sum over blocks of partials[b*nsums + i], in a fixed order: each workgroup owns 64
+// sums, four threads per sum add every fourth block, then the four parts are added in order.
 __global__ void __launch_bounds__(kBlock)
 k_reduce_partials(const double* __restrict__ partials, int nblocks, int nsums,
                   double* __restrict__ out) {
-  __shared__ double red[kBlock];
-  for (int i = 0; i < nsums; ++i) {
-    double t = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[(long long)b * nsums + i];
-    red[threadIdx.x] = t;
-    __syncthreads();
-    for (int h = kBlock / 2; h > 0; h >>= 1) {
-      if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[i] = red[0];
-    __syncthreads();
-  }
+  __shared__ double red[4][64];
+  const int t = threadIdx.x, col = t & 63, part = t >> 6;
+  const int i = blockIdx.x * 64 + col;
+  double acc = 0.0;
+  if (i < nsums)
+    for (int b = part; b < nblocks; b += 4) acc += partials[(long long)b * nsums + i];
+  red[part][col] = acc;
+  __syncthreads();
+  if (part == 0 && i < nsums) out[i] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
 }
 
 // Arnoldi bookkeeping for step j (one thread).
@@ -475,7 +486,8 @@ int launch_update_dot(long long n, const double* V, long long ldv, int nv, const
 int launch_reduce_partials(const double* partials, int nblocks, int nsums, double* out,
                            hipStream_t s) {
   prof_begin(KKTDD_K_ARNOLDI, s);
-  hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kBlock), 0, s, partials, nblocks, nsums, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3((nsums + 63) / 64), dim3(kBlock), 0, s, partials,
+                     nblocks, nsums, out);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_ARNOLDI, s, 8.0 * nblocks * nsums, 0.0);
   return 0;
@@ -494,37 +506,19 @@ int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const
 
 int launch_dcgs_dots(long long n, const double* V, long long ldv, int j, const double* Vc,
                      const double* W, double* partials, int nblocks, hipStream_t s) {
-  const dim3 grid(nblocks), block(kBlock);
   prof_begin(KKTDD_K_ARNOLDI, s);
-  if (j <= 8)
-    hipLaunchKernelGGL((k_dcgs_dots<8>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
-  else if (j <= 16)
-    hipLaunchKernelGGL((k_dcgs_dots<16>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
-  else if (j <= 24)
-    hipLaunchKernelGGL((k_dcgs_dots<24>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
-  else if (j <= 32)
-    hipLaunchKernelGGL((k_dcgs_dots<32>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
-  else
-    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblocks), dim3(kBlock), 0, s, n, V, ldv, j, Vc, W, partials);
   KKT_HIP(hipGetLastError());
-  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + (W ? 2 : 1)) * n, 0.0);
+  const int nchunks = j == 0 ? 1 : (j + kChunk - 1) / kChunk;
+  prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + nchunks * (W ? 2 : 1)) * n, 0.0);
   return 0;
 }
 
 int launch_dcgs_update(long long n, double* V, long long ldv, int j, const double* coef,
                        const int* gate, double* partials, int nblocks, hipStream_t s) {
-  const dim3 grid(nblocks), block(kBlock);
   prof_begin(KKTDD_K_ARNOLDI, s);
-  if (j <= 8)
-    hipLaunchKernelGGL((k_dcgs_update<8>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
-  else if (j <= 16)
-    hipLaunchKernelGGL((k_dcgs_update<16>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
-  else if (j <= 24)
-    hipLaunchKernelGGL((k_dcgs_update<24>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
-  else if (j <= 32)
-    hipLaunchKernelGGL((k_dcgs_update<32>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
-  else
-    return set_error(KKTDD_EINVAL, "more than 32 Krylov vectors per pass");
+  hipLaunchKernelGGL(k_dcgs_update, dim3(nblocks), dim3(kBlock), 0, s, n, V, ldv, j, coef, gate,
+                     partials);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + 4) * n, 0.0);
   return 0;

@@ -69,6 +69,25 @@ def test_validate_rejects_bad_problems(lib, bad):
     assert len(lib.kkt_last_error()) > 0
 
 
+def test_header_constants_match_the_binding():
+    from paper_2305_04421_amd import _lib
+    text = open(HEADER).read()
+    assert int(re.search(r"#define KKTDD_MAX_RESTART (\d+)", text).group(1)) == _lib.MAX_RESTART
+    for name, val in (("KKTDD_OK", _lib.OK), ("KKTDD_NOT_CONVERGED", _lib.NOT_CONVERGED),
+                      ("KKTDD_EINVAL", _lib.EINVAL), ("KKTDD_EBREAKDOWN", _lib.EBREAKDOWN),
+                      ("KKTDD_BF16X6", _lib.BF16X6), ("KKTDD_SWEEP_MODAL", _lib.SWEEP_MODAL)):
+        assert int(re.search(name + r"\s*=\s*(-?\d+)", text).group(1)) == val, name
+
+
+def test_memory_plan_of_a_long_cycle(lib):
+    # the unrestarted solves of the weak-scaling experiment keep up to 421 basis vectors
+    p = _prob(nx=16, ny=16, nt=256, n_sub=16)
+    b = ctypes.c_size_t()
+    assert lib.kkt_memory_plan(ctypes.byref(p), 420, ctypes.byref(b)) == 0
+    P = 15 * 15 * 256
+    assert b.value >= (421 * 3 + 420) * P * 8
+
+
 def test_memory_plan_grows_with_restart(lib):
     p = _prob(nx=128, ny=128, nt=256, n_sub=16)
     a, b = ctypes.c_size_t(), ctypes.c_size_t()
