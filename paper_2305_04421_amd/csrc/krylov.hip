@@ -3,12 +3,20 @@
 //
 // Krylov vectors are stored unnormalised: the basis vector is v_i = vinv[i] * V_i with the
 // scale vinv[i] kept on the device, so normalising a new vector costs no extra pass.
-// Arnoldi step j orthogonalises w = K z_j against v_0..v_j by classical Gram-Schmidt with
-// selective reorthogonalisation (Daniel-Gragg-Kaufman-Stewart): pass A forms <v_i, w> and
-// ||w||; pass B subtracts the projections and, reading the same V, also forms
-// <v_i, w1> and ||w1||; only if ||w1|| < eta ||w|| does pass C subtract the second
-// projections.  Every reduction is two-stage and in a fixed order, so results are
-// deterministic.
+//
+// Default orthogonalisation: delayed classical Gram-Schmidt with reorthogonalisation (DCGS2,
+// the one-synchronisation CGS2 of Swirydowicz, Langou, Ananthan, Yang and Thomas).  Step j
+// holds the not yet reorthogonalised candidate of v_j and W = K z_j; one inner-product pass
+// forms <V_i, candidate>, <V_i, W>, ||candidate||^2, <candidate, W> and ||W||^2, and one
+// update pass finishes v_j (second projection) and projects W once, which becomes the next
+// candidate.  The basis is walked in chunks, so a cycle may hold any number of vectors.
+//
+// Alternative: classical Gram-Schmidt with selective reorthogonalisation
+// (Daniel-Gragg-Kaufman-Stewart, at most 32 vectors per pass): pass A forms <v_i, w> and
+// ||w||; pass B subtracts the projections and, reading the same V, also forms <v_i, w1>
+// and ||w1||; only if ||w1|| < eta ||w|| does pass C subtract the second projections.
+//
+// Every reduction is two-stage and in a fixed order, so results are deterministic.
 #include "internal.h"
 
 namespace kktdd {
@@ -152,15 +160,16 @@ k_update_dot(long long n, const double* __restrict__ V, long long ldv, int nv,
 // and one pass applies them: the candidate is reorthogonalised into the final v_j and W is
 // projected once against v_0..v_j, becoming the next candidate.  So each step reads the basis
 // twice instead of three times (Swirydowicz et al. 2021; Bielich et al. 2022).
-// Inner products of a DCGS2 step for any j: the basis is processed in chunks of 32 vectors
-// (register accumulators), each chunk re-streaming the candidate and W.  Per-block partial
-// sums are laid out as [A_0..A_{j-1}, B_0..B_{j-1}, C, E, F].
-constexpr int kChunk = 32;
-
+// Inner products of a DCGS2 step for any j.  Per-block partial sums are laid out as
+// [A_0..A_{j-1}, B_0..B_{j-1}, C, E, F].  The basis is processed in chunks of CH vectors held
+// in register accumulators; each further chunk re-streams the candidate and W.
+template <int CH>
 __global__ void __launch_bounds__(kBlock)
 k_dcgs_dots(long long n, const double* __restrict__ V, long long ldv, int j,
             const double* __restrict__ Vc, const double* __restrict__ W,
             double* __restrict__ partials) {
+  constexpr int NS = 2 * CH + 3;
+  __shared__ double red[kBlock / 64][NS];
   const int ns = 2 * j + 3;
   const long long n2 = n >> 1, ld2 = ldv >> 1;
   const double2* __restrict__ V2 = reinterpret_cast<const double2*>(V);
@@ -169,70 +178,89 @@ k_dcgs_dots(long long n, const double* __restrict__ V, long long ldv, int j,
   const bool hasW = W != nullptr;
   const long long stride = (long long)gridDim.x * kBlock;
   const bool tail = (n & 1) && blockIdx.x == 0 && threadIdx.x == 0;
-  const int nchunks = j == 0 ? 1 : (j + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* out = partials + (long long)blockIdx.x * ns;
+  const int nchunks = j == 0 ? 1 : (j + CH - 1) / CH;
   for (int c = 0; c < nchunks; ++c) {
-    const int i0 = c * kChunk;
-    const int cnt = j - i0 < kChunk ? j - i0 : kChunk;   // may be <= 0 when j == 0
-    double acc[2 * kChunk + 3];
-#pragma unroll
-    for (int i = 0; i < 2 * kChunk + 3; ++i) acc[i] = 0.0;
+    const int i0 = c * CH;
+    const int cnt = j - i0 < CH ? j - i0 : CH;   // <= 0 only when j == 0
     const bool first = c == 0;
+    double acc[NS];
+#pragma unroll
+    for (int i = 0; i < NS; ++i) acc[i] = 0.0;
     for (long long e = (long long)blockIdx.x * kBlock + threadIdx.x; e < n2; e += stride) {
       const double2 cv = c2[e];
       const double2 w = hasW ? w2[e] : double2{0.0, 0.0};
 #pragma unroll
-      for (int i = 0; i < kChunk; ++i)
+      for (int i = 0; i < CH; ++i)
         if (i < cnt) {
           const double2 v = V2[(long long)(i0 + i) * ld2 + e];
           acc[i] += v.x * cv.x + v.y * cv.y;
-          acc[kChunk + i] += v.x * w.x + v.y * w.y;
+          acc[CH + i] += v.x * w.x + v.y * w.y;
         }
-      if (first) {
-        acc[2 * kChunk] += cv.x * cv.x + cv.y * cv.y;
-        acc[2 * kChunk + 1] += cv.x * w.x + cv.y * w.y;
-        acc[2 * kChunk + 2] += w.x * w.x + w.y * w.y;
-      }
+      acc[2 * CH] += cv.x * cv.x + cv.y * cv.y;
+      acc[2 * CH + 1] += cv.x * w.x + cv.y * w.y;
+      acc[2 * CH + 2] += w.x * w.x + w.y * w.y;
     }
     if (tail) {
       const double cv = Vc[n - 1], w = hasW ? W[n - 1] : 0.0;
 #pragma unroll
-      for (int i = 0; i < kChunk; ++i)
+      for (int i = 0; i < CH; ++i)
         if (i < cnt) {
           const double v = V[(long long)(i0 + i) * ldv + n - 1];
           acc[i] += v * cv;
-          acc[kChunk + i] += v * w;
+          acc[CH + i] += v * w;
         }
-      if (first) {
-        acc[2 * kChunk] += cv * cv;
-        acc[2 * kChunk + 1] += cv * w;
-        acc[2 * kChunk + 2] += w * w;
+      acc[2 * CH] += cv * cv;
+      acc[2 * CH + 1] += cv * w;
+      acc[2 * CH + 2] += w * w;
+    }
+    // wave sums, then thread t adds the four waves' value of slot t and stores it
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const bool used = (i < CH && i < cnt) || (i >= CH && i < 2 * CH && i - CH < cnt) ||
+                        (i >= 2 * CH && first);
+      if (used) {
+        const double v = wave_sum(acc[i]);
+        if (lane == 0) red[wave][i] = v;
       }
     }
-    double* out = partials + (long long)blockIdx.x * ns;
-    if (cnt > 0) {
-      block_sums<kChunk>(*reinterpret_cast<double(*)[kChunk]>(acc), cnt, out + i0);
-      __syncthreads();
-      block_sums<kChunk>(*reinterpret_cast<double(*)[kChunk]>(acc + kChunk), cnt, out + j + i0);
-      __syncthreads();
+    __syncthreads();
+    const int t = threadIdx.x;
+    if (t < NS) {
+      int dst = -1;
+      if (t < CH) dst = t < cnt ? i0 + t : -1;
+      else if (t < 2 * CH) dst = t - CH < cnt ? j + i0 + (t - CH) : -1;
+      else if (first) dst = 2 * j + (t - 2 * CH);
+      if (dst >= 0) {
+        double v = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) v += red[w][t];
+        out[dst] = v;
+      }
     }
-    if (first) {
-      block_sums<3>(*reinterpret_cast<double(*)[3]>(acc + 2 * kChunk), 3, out + 2 * j);
-      __syncthreads();
-    }
+    __syncthreads();
   }
 }
 
 // coef = [cv, hjj, p_0..p_{j-1}, q_0..q_{j-1}]:
 //   slot j   <- v  = cv * Vc - sum_i p_i V_i
 //   slot j+1 <- W' = W - sum_i q_i V_i - hjj * v,  with partial sums of ||W'||^2.
-// The coefficients are wave-uniform, so they are read through the scalar cache.
+// MAXV > 0: j <= MAXV, coefficients in registers.  MAXV == 0: any j, coefficients read per
+// use (wave-uniform loads).
+template <int MAXV>
 __global__ void __launch_bounds__(kBlock)
 k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __restrict__ coef,
               const int* __restrict__ gate, double* __restrict__ partials) {
   if (gate && *gate == 0) return;
   const double cv = coef[0], hjj = coef[1];
-  const double* p = coef + 2;
-  const double* q = coef + 2 + j;
+  constexpr int NR = MAXV > 0 ? MAXV : 1;
+  double p[NR], q[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    p[i] = (MAXV > 0 && i < j) ? coef[2 + i] : 0.0;
+    q[i] = (MAXV > 0 && i < j) ? coef[2 + j + i] : 0.0;
+  }
   const long long n2 = n >> 1, ld2 = ldv >> 1;
   double2* V2 = reinterpret_cast<double2*>(V);
   double2* c2 = V2 + (long long)j * ld2;
@@ -243,25 +271,39 @@ k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __rest
     const double2 c = c2[e];
     double2 w = w2[e];
     double2 v = {cv * c.x, cv * c.y};
-    int i = 0;
-    for (; i + 4 <= j; i += 4) {
-      double2 b[4];
+    if constexpr (MAXV > 0) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) b[u] = V2[(long long)(i + u) * ld2 + e];
+      for (int i = 0; i < MAXV; ++i)
+        if (i < j) {
+          const double2 b = V2[(long long)i * ld2 + e];
+          v.x -= p[i] * b.x;
+          v.y -= p[i] * b.y;
+          w.x -= q[i] * b.x;
+          w.y -= q[i] * b.y;
+        }
+    } else {
+      const double* pc = coef + 2;
+      const double* qc = coef + 2 + j;
+      int i = 0;
+      for (; i + 8 <= j; i += 8) {
+        double2 b[8];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        v.x -= p[i + u] * b[u].x;
-        v.y -= p[i + u] * b[u].y;
-        w.x -= q[i + u] * b[u].x;
-        w.y -= q[i + u] * b[u].y;
+        for (int u = 0; u < 8; ++u) b[u] = V2[(long long)(i + u) * ld2 + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          v.x -= pc[i + u] * b[u].x;
+          v.y -= pc[i + u] * b[u].y;
+          w.x -= qc[i + u] * b[u].x;
+          w.y -= qc[i + u] * b[u].y;
+        }
       }
-    }
-    for (; i < j; ++i) {
-      const double2 b = V2[(long long)i * ld2 + e];
-      v.x -= p[i] * b.x;
-      v.y -= p[i] * b.y;
-      w.x -= q[i] * b.x;
-      w.y -= q[i] * b.y;
+      for (; i < j; ++i) {
+        const double2 b = V2[(long long)i * ld2 + e];
+        v.x -= pc[i] * b.x;
+        v.y -= pc[i] * b.y;
+        w.x -= qc[i] * b.x;
+        w.y -= qc[i] * b.y;
+      }
     }
     w.x -= hjj * v.x;
     w.y -= hjj * v.y;
@@ -275,8 +317,8 @@ k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __rest
     double v = cv * c[n - 1], x = w[n - 1];
     for (int i = 0; i < j; ++i) {
       const double b = V[(long long)i * ldv + n - 1];
-      v -= p[i] * b;
-      x -= q[i] * b;
+      v -= coef[2 + i] * b;
+      x -= coef[2 + j + i] * b;
     }
     x -= hjj * v;
     c[n - 1] = v;
@@ -337,20 +379,19 @@ __global__ void k_dcgs_finish(int j, const double* __restrict__ sums, double* __
   }
 }
 
-// out[i] = sum over blocks of partials[b*nsums + i], in a fixed order: each workgroup owns 64
-// sums, four threads per sum add every fourth block, then the four parts are added in order.
+// out[i] = sum over blocks of partials[b*nsums + i] in a fixed order: workgroup i sums
+// column i, thread t taking blocks t, t+256, ..., then a fixed-shape tree over the threads.
 __global__ void __launch_bounds__(kBlock)
 k_reduce_partials(const double* __restrict__ partials, int nblocks, int nsums,
                   double* __restrict__ out) {
-  __shared__ double red[4][64];
-  const int t = threadIdx.x, col = t & 63, part = t >> 6;
-  const int i = blockIdx.x * 64 + col;
-  double acc = 0.0;
-  if (i < nsums)
-    for (int b = part; b < nblocks; b += 4) acc += partials[(long long)b * nsums + i];
-  red[part][col] = acc;
+  __shared__ double red[kBlock / 64];
+  const int i = blockIdx.x;
+  double t = 0.0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) t += partials[(long long)b * nsums + i];
+  t = wave_sum(t);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
   __syncthreads();
-  if (part == 0 && i < nsums) out[i] = ((red[0][col] + red[1][col]) + red[2][col]) + red[3][col];
+  if (threadIdx.x == 0) out[i] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // Arnoldi bookkeeping for step j (one thread).
@@ -486,8 +527,8 @@ int launch_update_dot(long long n, const double* V, long long ldv, int nv, const
 int launch_reduce_partials(const double* partials, int nblocks, int nsums, double* out,
                            hipStream_t s) {
   prof_begin(KKTDD_K_ARNOLDI, s);
-  hipLaunchKernelGGL(k_reduce_partials, dim3((nsums + 63) / 64), dim3(kBlock), 0, s, partials,
-                     nblocks, nsums, out);
+  hipLaunchKernelGGL(k_reduce_partials, dim3(nsums), dim3(kBlock), 0, s, partials, nblocks,
+                     nsums, out);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_ARNOLDI, s, 8.0 * nblocks * nsums, 0.0);
   return 0;
@@ -506,19 +547,35 @@ int launch_arnoldi_finish(int j, const double* sums1, const double* sums2, const
 
 int launch_dcgs_dots(long long n, const double* V, long long ldv, int j, const double* Vc,
                      const double* W, double* partials, int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks), block(kBlock);
   prof_begin(KKTDD_K_ARNOLDI, s);
-  hipLaunchKernelGGL(k_dcgs_dots, dim3(nblocks), dim3(kBlock), 0, s, n, V, ldv, j, Vc, W, partials);
+  // 8- and 16-vector chunks keep the accumulators in few enough registers for full
+  // occupancy; wider chunks read the candidate and W fewer times but stream more slowly.
+  const int ch = j <= 8 ? 8 : 16;
+  if (ch == 8)
+    hipLaunchKernelGGL((k_dcgs_dots<8>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
+  else
+    hipLaunchKernelGGL((k_dcgs_dots<16>), grid, block, 0, s, n, V, ldv, j, Vc, W, partials);
   KKT_HIP(hipGetLastError());
-  const int nchunks = j == 0 ? 1 : (j + kChunk - 1) / kChunk;
+  const int nchunks = j == 0 ? 1 : (j + ch - 1) / ch;
   prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + nchunks * (W ? 2 : 1)) * n, 0.0);
   return 0;
 }
 
 int launch_dcgs_update(long long n, double* V, long long ldv, int j, const double* coef,
                        const int* gate, double* partials, int nblocks, hipStream_t s) {
+  const dim3 grid(nblocks), block(kBlock);
   prof_begin(KKTDD_K_ARNOLDI, s);
-  hipLaunchKernelGGL(k_dcgs_update, dim3(nblocks), dim3(kBlock), 0, s, n, V, ldv, j, coef, gate,
-                     partials);
+  if (j <= 8)
+    hipLaunchKernelGGL((k_dcgs_update<8>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 16)
+    hipLaunchKernelGGL((k_dcgs_update<16>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 24)
+    hipLaunchKernelGGL((k_dcgs_update<24>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else if (j <= 32)
+    hipLaunchKernelGGL((k_dcgs_update<32>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
+  else
+    hipLaunchKernelGGL((k_dcgs_update<0>), grid, block, 0, s, n, V, ldv, j, coef, gate, partials);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_ARNOLDI, s, 8.0 * (j + 4) * n, 0.0);
   return 0;
