@@ -214,6 +214,32 @@ def test_modal_solve_matches_dense_solve(kw):
     np.testing.assert_allclose(xm, xd, rtol=1e-10, atol=1e-10 * np.abs(xd).max())
 
 
+def test_sine_coefficients_of_a_single_mode():
+    # sin(a pi x/Lx) sin(b pi y/Ly) has coefficient (nx/2)(ny/2) at mode (b-1, a-1), 0 elsewhere
+    p = _tiny(nx=7, ny=5, nt=2, n_sub=1, overlap=0, coarse=0)
+    x = np.arange(1, p.nx) * p.dx
+    y = np.arange(1, p.ny) * p.dy
+    v = np.sin(3 * np.pi * x / p.Lx)[None, :] * np.sin(2 * np.pi * y / p.Ly)[:, None]
+    modes = [(q, pm) for q in range(p.my) for pm in range(p.mx)]
+    c = dr.sine_coefficients(p, v, modes)
+    want = np.zeros(len(modes))
+    want[modes.index((1, 2))] = (p.nx / 2) * (p.ny / 2)
+    np.testing.assert_allclose(c, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("kw", [dict(), dict(nx=5, ny=9, nt=7, omega=1e-4)])
+def test_sampled_modes_match_dense_solve(kw):
+    p = _tiny(**dict(kw, n_sub=1, overlap=0, coarse=0))
+    rng = np.random.default_rng(8)
+    u0 = rng.standard_normal(p.slice_shape)
+    ut = rng.standard_normal(p.field_shape)
+    xd = dr.dense_solve(p, op.rhs(p, u0, ut))
+    modes = [(0, 0), (p.my - 1, 0), (p.my // 2, p.mx - 1), (p.my - 1, p.mx - 1)]
+    got = dr.modal_solve_modes(p, u0, ut, modes)
+    want = dr.sine_coefficients(p, xd, modes)   # (modes, 3, nt)
+    np.testing.assert_allclose(got, want, rtol=1e-9, atol=1e-10 * np.abs(want).max())
+
+
 # ---- the block preconditioner and S_hat ------------------------------------------------------
 
 def test_exact_schur_block_preconditioner_three_eigenvalues():
