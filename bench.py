@@ -34,11 +34,27 @@ METRIC = "KKT space-time unknowns solved/s to 1e-8 rel. residual, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 WORKLOAD_SETS = {
-    # the two problems one step solves (one batch)
+    # the problems one step solves (one batch)
     "grid128": ("grid128", "grid128_w4"),
     "grid256": ("grid256",),
     "grid512": ("grid512",),
+    "uneven64": "uneven64",
 }
+# restart length per workload: the Krylov basis of the largest ones must fit in HBM
+DEFAULT_RESTART = {"grid512": 12, "uneven64": 12}
+# reduced-precision paths timed per workload (the largest ones time a subset)
+# ("auto": float32 sweeps per problem where kappa(D_sigma) <= 500, else float64)
+DEFAULT_MIXED = {"grid512": ("fp32", "bf16x6"), "uneven64": ("auto",)}
+DEFAULT_HOISTED = {"grid512": ("fp64", "fp32"), "uneven64": ("fp64", "auto")}
+
+
+def workload_problems(key):
+    """[(name, params, recipe)] of a workload set."""
+    from paper_2305_04421_amd import workloads as wl
+    if key == "uneven64":
+        return [(f"uneven{i:02d}", params, recipe)
+                for i, (params, recipe) in enumerate(wl.batch_uneven(64, seed=4))]
+    return [(name,) + wl.config(name) for name in WORKLOAD_SETS[key]]
 MIXED = ("fp32", "bf16x6", "bf16x3", "bf16")
 DESCRIPTIONS = {
     "grid128": "grid128: 127x127 interior x nt=256, T=1, nu=1, omega {1e-2, 1e-4}, 16 time subdomains, "
@@ -47,12 +63,16 @@ DESCRIPTIONS = {
                "overlap 2, constant+linear coarse basis, target with 1e-3 noise",
     "grid512": "grid512: 511x511 interior x nt=2048, T=1, nu=1, omega 1e-4, 128 time subdomains, "
                "overlap 4, constant+linear coarse basis",
+    "uneven64": "uneven64: 64 independent problems, n in {64,96,128,192,256}, nt = 16*U{4..32}, "
+                "nu log-uniform [0.05,1], omega log-uniform [1e-4,1e-1], nt/16 time subdomains, overlap 2, "
+                "constant+linear coarse basis",
 }
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE (FETCH_SIZE scaled by 2.0,
-# WRITE_SIZE by 1.0: what a 1 GiB device copy reads on those counters), per kernel class, as
-# recorded in profiles/arnoldi_grid128_fp64_hbm_counters.md for the current kernels.  A class
-# whose kernels changed since the counters were taken is absent (traffic null).
-TRAFFIC = {"arnoldi": 496.85e6, "matvec": 215.83e6}
+# WRITE_SIZE by 1.0: what a 1 GiB device copy reads on those counters), per workload and
+# kernel class, as recorded in profiles/arnoldi_<workload>_fp64_hbm_counters.md for the
+# current kernels.  A class whose kernels changed since the counters were taken, or a
+# workload without counters, is absent (traffic null).
+TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.83e6}}
 
 
 def parse():
@@ -60,7 +80,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--restart", type=int, default=None,
+                    help="FGMRES restart length (default 30; 12 for grid512 and uneven64)")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--cpu-iters", type=int, default=4,
                     help="FGMRES iterations of the CPU oracle sample (0: skip the CPU baseline)")
@@ -96,15 +117,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.restart is None:
+        args.restart = DEFAULT_RESTART.get(args.workload, 30)
     probs = []
-    WORKLOADS = WORKLOAD_SETS[args.workload]
-    for name in WORKLOADS:
-        params, recipe = wl.config(name)
+    recipes = {}
+    for name, params, recipe in workload_problems(args.workload):
         u0, ut = wl.data(params, recipe)
+        recipes[name] = recipe
         probs.append((name, params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
+        del u0, ut
     unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
 
-    def run_path(precision, steps, warmup, profile, sweep="step"):
+    def run_path(precision, steps, warmup, profile, sweep="step", must_converge=True):
         solvers = [KKTSolver(p, precision, sweep=sweep) for _, p, _, _ in probs]
         fs = [S.rhs(u0, ut) for S, (_, _, u0, ut) in zip(solvers, probs)]
         xs = [torch.zeros_like(f) for f in fs]
@@ -118,9 +142,9 @@ def main():
                        for S, f, x in zip(solvers, fs, xs)]
             else:
                 _, out = solve_batched(solvers, fs, xs, restart=args.restart, maxit=600, rtol=args.rtol)
-            for st in out:
-                if st["status"] != 0:
-                    raise RuntimeError(f"{precision} solve did not converge: {st}")
+            for (name, _, _, _), st in zip(probs, out):
+                if st["status"] != 0 and must_converge:
+                    raise RuntimeError(f"{precision} solve of {name} did not converge: {st}")
             return out
 
         for _ in range(warmup):
@@ -162,7 +186,7 @@ def main():
         "config": {"workload": DESCRIPTIONS[args.workload] + ", FGMRES(%d) to %g from x0=0, %s" % (
                                    args.restart, args.rtol,
                                    "solved one after another" if args.sequential else "solved as one batch"),
-                   "unknowns_per_step": sum(unknowns), "problems": list(WORKLOADS)},
+                   "unknowns_per_step": sum(unknowns), "problems": [name for name, _, _, _ in probs]},
         "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st64)},
         "reorthogonalised_steps": {name: st["reorth"] for (name, _, _, _), st in zip(probs, st64)},
         "batched": not args.sequential,
@@ -185,7 +209,7 @@ def main():
     d = prof64[dom]
     total_ms = sum(v["ms"] for v in prof64.values())
     roof = class_roof(dom)
-    roof["traffic"] = TRAFFIC.get(dom)
+    roof["traffic"] = TRAFFIC.get(args.workload, {}).get(dom)
     roof["kernel_class"] = dom
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = 1e3 * d["ms"] / max(d["launches"], 1)
@@ -203,7 +227,11 @@ def main():
     result["roofline"] = roof
 
     def summary(prec, sweep):
-        dt, st, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep)
+        dt, st, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep, must_converge=False)
+        failed = [name for (name, _, _, _), x in zip(probs, st) if x["status"] != 0]
+        if failed:
+            return {"value": None, "not_converged": failed, "ms_per_step": 1e3 * dt / args.steps,
+                    "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)}}
         v = args.steps * sum(unknowns) / dt
         return {"value": v, "ms_per_step": 1e3 * dt / args.steps, "ratio_vs_fp64": v / value64,
                 "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
@@ -212,22 +240,30 @@ def main():
     if not args.no_mixed:
         # reduced-precision sweeps and sine-transform GEMMs; FGMRES, matvec and coarse level
         # stay float64 (FGMRES acting as iterative refinement)
-        result["mixed"] = {prec: summary(prec, "step") for prec in MIXED}
+        result["mixed"] = {prec: summary(prec, "step") for prec in DEFAULT_MIXED.get(args.workload, MIXED)}
 
     if not args.no_hoisted:
         # transform-hoisted Schur block (sine-mode sweeps), measured beside the per-step path
-        result["hoisted"] = {prec: summary(prec, "modal") for prec in ("fp64",) + MIXED}
+        result["hoisted"] = {prec: summary(prec, "modal")
+                             for prec in DEFAULT_HOISTED.get(args.workload, ("fp64",) + MIXED)}
 
     if args.cpu_iters > 0:
-        result["cpu_baseline"] = cpu_baseline(args, probs[0][0], probs[0][1], st64[0]["iters"])
+        result["cpu_baseline"] = cpu_baseline(args, probs[0][0], probs[0][1], recipes[probs[0][0]],
+                                              st64[0]["iters"])
 
     print(json.dumps(result), flush=True)
     return 0
 
 
-def cpu_baseline(args, name, params, iters_full):
+# Above this many KKT unknowns the CPU sample is a time-truncated copy of the problem.
+CPU_FULL_LIMIT = 50_000_000
+
+
+def cpu_baseline(args, name, params, recipe, iters_full):
     """The CPU oracle on a bounded sample: its first `cpu_iters` FGMRES iterations of the
-    step's first problem, scaled to the iteration count of the full solve."""
+    step's first problem, scaled to the iteration count of the full solve.  Problems above
+    CPU_FULL_LIMIT unknowns are sampled on their first 64 time steps (same grid, time step,
+    steps per subdomain and overlap) and scaled per unknown-iteration."""
     import numpy as np
     from oracle.problem import Problem
     from oracle import operators as op, precond as pc, gmres as gm
@@ -237,20 +273,30 @@ def cpu_baseline(args, name, params, iters_full):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = None
-    p = Problem(**params).validate()
-    u0, ut = wl.data(params, wl.config(name)[1])
+    full = Problem(**params).validate()
+    sample_params = dict(params)
+    truncated = full.size > CPU_FULL_LIMIT
+    if truncated:
+        k = params["nt"] // params["n_sub"]
+        nt = 64
+        sample_params.update(nt=nt, T=params["T"] * nt / params["nt"], n_sub=nt // k)
+    p = Problem(**sample_params).validate()
+    u0, ut = wl.data(sample_params, recipe)
     f = op.rhs(p, u0, ut)
     t0 = time.perf_counter()
     res = gm.gmres(lambda v: op.apply_K(p, v), lambda v: pc.apply_Pinv(p, v), f,
                    restart=args.restart, maxit=args.cpu_iters, rtol=args.rtol)
     dt = time.perf_counter() - t0
     per_iter = dt / max(res.iterations, 1)
-    unknowns = p.size
-    return {"value": unknowns / (per_iter * iters_full), "unit": "unknowns/s", "cores": threads,
+    what = (f"the first {p.nt} time steps ({p.n_sub} subdomains) of the {name} problem"
+            if truncated else f"the {name} solve")
+    return {"value": p.size / (per_iter * iters_full), "unit": "unknowns/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"first {res.iterations} FGMRES({args.restart}) iterations of the {name} "
-                      f"solve ({dt:.1f} s incl. the initial residual), scaled to the {iters_full} "
-                      f"iterations of the full solve; numpy float64 with {threads} BLAS threads"}
+            "sample": f"first {res.iterations} FGMRES({args.restart}) iterations of {what} "
+                      f"({dt:.1f} s incl. the initial residual), scaled to the {iters_full} "
+                      f"iterations of the full solve"
+                      + (" and per unknown-iteration to the full problem" if truncated else "")
+                      + f"; numpy float64 with {threads} BLAS threads"}
 
 
 if __name__ == "__main__":

@@ -60,7 +60,8 @@ enum kktdd_precision {
   KKTDD_FP32 = 1,   /* float32 MFMA, float32 sweep state; float64 outer refinement          */
   KKTDD_BF16 = 2,   /* bfloat16 MFMA, float32 accumulation and sweep state                  */
   KKTDD_BF16X3 = 3, /* each float32 operand split into 2 bfloat16 parts, 3 part products    */
-  KKTDD_BF16X6 = 4  /* each float32 operand split into 3 bfloat16 parts, 6 part products    */
+  KKTDD_BF16X6 = 4, /* each float32 operand split into 3 bfloat16 parts, 6 part products    */
+  KKTDD_AUTO = 5    /* resolved by kkt_create: FP32 if kkt_kappa(prob) <= 500, else FP64    */
 };
 
 /* Placement of the spatial transforms in the fine-level sweeps.  Both compute the same
@@ -124,6 +125,14 @@ void kkt_destroy(kktdd_handle* h);
 
 /* Number of KKT unknowns, 3*nt*(nx-1)*(ny-1); 0 for NULL. */
 size_t kkt_size(const kktdd_handle* h);
+
+/* The precision the handle's sweeps run in (KKTDD_AUTO resolved); KKTDD_EINVAL for NULL. */
+int kkt_precision(const kktdd_handle* h);
+
+/* Condition number of the spatial block D_sigma = sigma*I + dt*nu*A_h of the preconditioner's
+ * sweeps (Eq. (7) with the shift of Sec. 2), from the extreme sine-mode eigenvalues of A_h.
+ * Float32 rounding in the sweeps is amplified by it.  Host-only; -1 for an invalid problem. */
+double kkt_kappa(const kktdd_problem* prob);
 
 /* Right-hand side of Eq. (5): f_u = h*utilde(t_n), f_z = 0, f_w = (u0, 0, ..., 0)
  * (Sec. 2: f carries the initial condition).

@@ -16,7 +16,7 @@ import ctypes
 from . import _lib
 from ._lib import KKTDDError  # noqa: F401
 
-__all__ = ["KKTSolver", "KKTDDError", "validate", "memory_plan", "library_path", "solve_batched"]
+__all__ = ["KKTSolver", "KKTDDError", "validate", "memory_plan", "kappa", "library_path", "solve_batched"]
 
 
 def library_path():
@@ -27,6 +27,15 @@ def validate(params, precision="fp64", sweep="step"):
     """Host-only parameter check (no device); raises KKTDDError on a bad problem."""
     prob = _lib.make_problem(params, precision, sweep)
     _lib.check(_lib.load().kkt_validate(ctypes.byref(prob)), "kkt_validate")
+
+
+def kappa(params):
+    """Condition number of the sweeps' spatial block D_sigma (host-only)."""
+    prob = _lib.make_problem(params, "fp64", "step")
+    v = _lib.load().kkt_kappa(ctypes.byref(prob))
+    if v < 0:
+        raise _lib.KKTDDError(_lib.EINVAL, "kkt_kappa: invalid problem")
+    return v
 
 
 def memory_plan(params, precision="fp64", restart=0, sweep="step"):
@@ -52,7 +61,8 @@ def _ptr(t, numel, name):
 class KKTSolver:
     """One problem handle on the current device and torch's current stream.
 
-    precision: "fp64" or "fp32" (sweeps and their sine-transform GEMMs);
+    precision: "fp64", "fp32", "bf16x6", "bf16x3", "bf16" (sweeps and their sine-transform
+        GEMMs), or "auto" (float32 when the spatial block is well conditioned, else float64);
     sweep: "step" (a spatial solve at every sweep step) or "modal" (transforms hoisted).
     """
 
@@ -72,6 +82,8 @@ class KKTSolver:
         self.my = params["ny"] - 1
         self.nt = params["nt"]
         self.size = lib.kkt_size(self._h)
+        # the precision the sweeps run in ("auto" resolved by the library)
+        self.resolved_precision = _lib.PRECISION_NAMES[lib.kkt_precision(self._h)]
 
     # ---- lifetime -------------------------------------------------------------------------
     def close(self):

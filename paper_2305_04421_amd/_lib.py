@@ -14,15 +14,17 @@ LIB_PATH = os.path.join(HERE, "libkktdd.so")
 # enum kktdd_status
 OK, NOT_CONVERGED, EINVAL, ENOMEM, EHIP, EBREAKDOWN = 0, 1, -1, -2, -3, -4
 # enum kktdd_precision
-FP64, FP32, BF16, BF16X3, BF16X6 = 0, 1, 2, 3, 4
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3, "bf16x6": BF16X6}
+FP64, FP32, BF16, BF16X3, BF16X6, AUTO = 0, 1, 2, 3, 4, 5
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3, "bf16x6": BF16X6, "auto": AUTO}
+PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 # enum kktdd_sweep
 SWEEP_STEP, SWEEP_MODAL = 0, 1
 SWEEPS = {"step": SWEEP_STEP, "modal": SWEEP_MODAL}
 # longest Arnoldi cycle of fgmres_solve
 MAX_RESTART = 1024
 
-EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_rhs",
+EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_precision",
+            "kkt_kappa", "kkt_rhs",
             "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
             "kkt_profile_read", "kkt_last_error")
 
@@ -71,6 +73,10 @@ def load():
     lib.kkt_destroy.restype = None
     lib.kkt_size.argtypes = [vp]
     lib.kkt_size.restype = sz
+    lib.kkt_precision.argtypes = [vp]
+    lib.kkt_precision.restype = ctypes.c_int
+    lib.kkt_kappa.argtypes = [P]
+    lib.kkt_kappa.restype = dbl
     lib.kkt_rhs.argtypes = [vp, vp, vp, vp]
     lib.kkt_apply.argtypes = [vp, vp, vp]
     lib.precond_apply.argtypes = [vp, vp, vp]

@@ -194,13 +194,39 @@ int validate(const kktdd_problem* p) {
   if (p->overlap < 0 || p->overlap > k) return bad("overlap must satisfy 0 <= overlap <= nt/n_sub");
   if (p->coarse < 0 || p->coarse > 2) return bad("coarse must be 0, 1 or 2");
   if (p->coarse == 2 && k < 2) return bad("a linear coarse basis needs nt/n_sub >= 2");
-  if (p->precision < KKTDD_FP64 || p->precision > KKTDD_BF16X6) return bad("unknown precision");
+  if (p->precision < KKTDD_FP64 || p->precision > KKTDD_AUTO) return bad("unknown precision");
   if (p->sweep != KKTDD_SWEEP_STEP && p->sweep != KKTDD_SWEEP_MODAL) return bad("unknown sweep placement");
   if ((long long)p->nt * (p->nx - 1) * (p->ny - 1) > (1LL << 40)) return bad("problem too large");
   return KKTDD_OK;
 }
 
 bool is_bf16(int precision) { return precision >= KKTDD_BF16 && precision <= KKTDD_BF16X6; }
+
+// Condition number of D_sigma = sigma I + dt nu A_h: the ratio of its extreme eigenvalues
+// sigma + dt nu (lambda^x_p + lambda^y_q), lambda_p = (4/dx^2) sin^2(p pi / (2 nx)).
+double kappa_D(const kktdd_problem& p) {
+  const double dx = p.Lx / p.nx, dy = p.Ly / p.ny, dt = p.T / p.nt;
+  const double sigma = 1.0 + dt / std::sqrt(p.omega);
+  auto lam = [](int i, int n, double d) {
+    const double s = std::sin(i * 3.14159265358979323846 / (2.0 * n));
+    return 4.0 / (d * d) * s * s;
+  };
+  const double lo = lam(1, p.nx, dx) + lam(1, p.ny, dy);
+  const double hi = lam(p.nx - 1, p.nx, dx) + lam(p.ny - 1, p.ny, dy);
+  return (sigma + dt * p.nu * hi) / (sigma + dt * p.nu * lo);
+}
+
+// KKTDD_AUTO: float32 sweeps while kappa(D_sigma) <= kAutoKappaFp32, else float64.  Rounding
+// of the float32 transforms is amplified by kappa in the sweep output; up to this bound
+// the float64 FGMRES iteration count stays within two of the float64 path on the uneven
+// batch workload, beyond it float32 sweeps can stall the outer iteration.
+constexpr double kAutoKappaFp32 = 500.0;
+
+kktdd_problem resolve(const kktdd_problem& p) {
+  kktdd_problem r = p;
+  if (r.precision == KKTDD_AUTO) r.precision = kappa_D(p) <= kAutoKappaFp32 ? KKTDD_FP32 : KKTDD_FP64;
+  return r;
+}
 
 Geom make_geom(const kktdd_problem& p) {
   Geom g{};
@@ -565,14 +591,17 @@ int kkt_validate(const kktdd_problem* prob) { return validate(prob); }
 int kkt_memory_plan(const kktdd_problem* prob, int32_t restart, size_t* bytes) {
   if (int e = validate(prob)) return e;
   if (!bytes || restart < 0) return set_error(KKTDD_EINVAL, "bad memory-plan arguments");
-  *bytes = plan(make_geom(*prob), prob->precision, prob->sweep, restart).total();
+  const kktdd_problem rp = resolve(*prob);
+  *bytes = plan(make_geom(rp), rp.precision, rp.sweep, restart).total();
   return KKTDD_OK;
 }
 
-int kkt_create(const kktdd_problem* prob, void* hip_stream, kktdd_handle** out) {
+int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** out) {
   if (!out) return set_error(KKTDD_EINVAL, "out is NULL");
   *out = nullptr;
-  if (int e = validate(prob)) return e;
+  if (int e = validate(prob_in)) return e;
+  const kktdd_problem resolved = resolve(*prob_in);
+  const kktdd_problem* prob = &resolved;
   kktdd_handle* H = new (std::nothrow) kktdd_handle;
   if (!H) return set_error(KKTDD_ENOMEM, "host allocation failed");
   H->prob = *prob;
@@ -667,6 +696,13 @@ void kkt_destroy(kktdd_handle* H) {
 }
 
 size_t kkt_size(const kktdd_handle* H) { return H ? (size_t)(3 * H->g.P) : 0; }
+
+int kkt_precision(const kktdd_handle* H) { return H ? H->prob.precision : KKTDD_EINVAL; }
+
+double kkt_kappa(const kktdd_problem* prob) {
+  if (!prob || validate(prob) != KKTDD_OK) return -1.0;
+  return kappa_D(*prob);
+}
 
 int kkt_rhs(kktdd_handle* H, const double* u0, const double* utilde, double* f) {
   ProfScope ps(H);

@@ -53,7 +53,7 @@ def test_validate_accepts_the_configurations(lib):
     from paper_2305_04421_amd import workloads as wl
     for name in ("tiny32", "grid128", "grid128_w4", "grid256", "grid512"):
         params, _ = wl.config(name)
-        for prec in ("fp64", "fp32", "bf16", "bf16x3", "bf16x6"):
+        for prec in ("fp64", "fp32", "bf16", "bf16x3", "bf16x6", "auto"):
             p = _prob(**dict(params, precision=prec))
             assert lib.kkt_validate(ctypes.byref(p)) == 0, name
 
@@ -61,7 +61,7 @@ def test_validate_accepts_the_configurations(lib):
 @pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(nx=1025), dict(nt=0), dict(omega=0.0),
                                  dict(nu=-1.0), dict(T=float("inf")), dict(Lx=0.0), dict(n_sub=5),
                                  dict(overlap=9), dict(overlap=-1), dict(coarse=3), dict(n_sub=32, coarse=2),
-                                 dict(precision=7), dict(sweep=2)])
+                                 dict(precision=6), dict(sweep=2)])
 def test_validate_rejects_bad_problems(lib, bad):
     from paper_2305_04421_amd import _lib
     p = _prob(**bad)
@@ -77,6 +77,33 @@ def test_header_constants_match_the_binding():
                       ("KKTDD_EINVAL", _lib.EINVAL), ("KKTDD_EBREAKDOWN", _lib.EBREAKDOWN),
                       ("KKTDD_BF16X6", _lib.BF16X6), ("KKTDD_SWEEP_MODAL", _lib.SWEEP_MODAL)):
         assert int(re.search(name + r"\s*=\s*(-?\d+)", text).group(1)) == val, name
+
+
+def test_kappa_matches_the_sine_mode_eigenvalues(lib):
+    import math
+    from oracle.problem import Problem
+    from oracle.spatial import laplacian_eigenvalues_1d
+    from paper_2305_04421_amd import kappa, workloads as wl
+    for name in ("tiny32", "grid128", "grid256", "grid512"):
+        params, _ = wl.config(name)
+        p = Problem(**params).validate()
+        lx = laplacian_eigenvalues_1d(p.nx, p.dx)
+        ly = laplacian_eigenvalues_1d(p.ny, p.dy)
+        d = p.sigma + p.dt * p.nu * (ly[:, None] + lx[None, :])
+        assert math.isclose(kappa(params), d.max() / d.min(), rel_tol=1e-12), name
+    assert lib.kkt_kappa(ctypes.byref(_prob(nx=1))) == -1.0
+
+
+def test_auto_precision_is_accepted_and_planned_like_its_resolution(lib):
+    from paper_2305_04421_amd import memory_plan
+    stiff = dict(nx=256, ny=256, nt=240, nu=0.81, omega=2.1e-2, n_sub=15, overlap=2)   # kappa > 500
+    mild = dict(nx=32, ny=32, nt=32, n_sub=4, overlap=2)                                # kappa 133
+    for kw, want in ((stiff, "fp64"), (mild, "fp32")):
+        p = _prob(**dict(kw, precision="auto"))
+        assert lib.kkt_validate(ctypes.byref(p)) == 0
+        params = dict(Lx=1.0, Ly=1.0, T=1.0, coarse=2, nu=1.0, omega=1e-2)
+        params.update(kw)
+        assert memory_plan(params, "auto", 10) == memory_plan(params, want, 10)
 
 
 def test_memory_plan_of_a_long_cycle(lib):

@@ -204,6 +204,24 @@ def test_reduced_precision_sweeps_reach_float64_tolerance(sweep, precision):
     assert np.linalg.norm(f - op.apply_K(p, xrh)) <= 1e-8 * np.linalg.norm(f)
 
 
+def test_auto_precision_resolves_by_kappa():
+    from paper_2305_04421_amd import kappa
+    params, recipe = wl.config("tiny32")            # kappa 133: float32 sweeps
+    assert kappa(params) < 500
+    with solver(params, "auto") as S:
+        assert S.resolved_precision == "fp32"
+    stiff, recipe = wl.batch_uneven(64, seed=4)[50]  # kappa 1617: float32 sweeps stall here
+    assert kappa(stiff) > 500
+    u0, ut = wl.data(stiff, recipe)
+    with solver(stiff, "auto") as Sa, solver(stiff, "fp64") as S64:
+        assert Sa.resolved_precision == "fp64"
+        fa = Sa.rhs(dev(u0), dev(ut))
+        xa, sta = Sa.solve(fa, restart=12, maxit=100, rtol=1e-8)
+        x64, st64 = S64.solve(fa, restart=12, maxit=100, rtol=1e-8)
+    assert sta["status"] == 0 and sta["iters"] == st64["iters"]
+    assert torch.equal(xa, x64)
+
+
 def test_fgmres_edge_cases():
     params = CASES["tiny_ragged"]
     p = Problem(**params).validate()
