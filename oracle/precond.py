@@ -49,18 +49,47 @@ def adjoint_sweep(p: Problem, b, nodes):
     return x
 
 
+def exact_local_solve(p: Problem, r, nodes):
+    """x = (R_s S_hat R_s^T)^{-1} R_s r on `nodes`: the local inverse of Eq. (9), with
+    S_hat = J_hat M_u^{-1} J_hat^T = (1/h) J_hat J_hat^T.  Returns {node: x^node}.
+
+    J_hat J_hat^T is block tridiagonal in time with blocks that are polynomials in A_h:
+    D_sigma^2 + I on the diagonal (D_sigma^2 at node 1, which has no earlier step) and
+    -D_sigma off it.  Every block is diagonal in the sine modes, so the restricted system
+    splits into one tridiagonal system per mode (d = sigma + dt*nu*lambda_pq).
+    """
+    L = len(nodes)
+    d = p.sigma + p.dt * p.nu * mode_eigenvalues(p)                  # (my, mx)
+    rhat = np.stack([dst2(p, r[n - 1]) for n in nodes])               # (L, my, mx)
+    T = np.zeros(d.shape + (L, L))
+    for i, n in enumerate(nodes):
+        T[..., i, i] = d * d + (1.0 if n >= 2 else 0.0)
+        if i > 0:
+            T[..., i, i - 1] = -d
+            T[..., i - 1, i] = -d
+    rhs = np.moveaxis(rhat, 0, -1)[..., None]                         # (my, mx, L, 1)
+    xhat = np.moveaxis(np.linalg.solve(T / p.h, rhs)[..., 0], -1, 0)   # (L, my, mx)
+    return {n: idst2(p, xhat[i]) for i, n in enumerate(nodes)}
+
+
 def rasq(p: Problem, r):
     """One-level RASQ of Eq. (13): sum_s R_s^T D_s (J_hat_s^{-T} M_s J_hat_s^{-1}) R_s r.
 
     Per subdomain: forward sweep, scale by the mass h, adjoint sweep, keep the owned nodes.
+    Variants: local == "exact" replaces the two sweeps by the local inverse of Eq. (9);
+    schwarz == "asm" keeps every node of the subdomain (no partition of unity), so
+    overlapping nodes receive the sum of their subdomains' values.
     """
     out = np.zeros(p.field_shape)
     for s in range(1, p.n_sub + 1):
         nodes = subdomain_nodes(p, s)
-        y = forward_sweep(p, r, nodes)
-        hy = {n: p.h * y[n] for n in nodes}
-        x = adjoint_sweep(p, hy, nodes)
-        for n in owned_nodes(p, s):
+        if p.local == "exact":
+            x = exact_local_solve(p, r, nodes)
+        else:
+            y = forward_sweep(p, r, nodes)
+            hy = {n: p.h * y[n] for n in nodes}
+            x = adjoint_sweep(p, hy, nodes)
+        for n in (owned_nodes(p, s) if p.schwarz == "ras" else nodes):
             out[n - 1] += x[n]
     return out
 
@@ -151,9 +180,17 @@ def schur_inverse(p: Problem, r):
     the fine level on the remaining residual:
         c = Q_0 r,  z = c + S_RASQ^{-1} (r - S_hat c),
     whose error propagator is (I - S_RASQ^{-1} S_hat)(I - Q_0 S_hat).
+    Variants: combine == "fine_first" applies the fine level first,
+        y = S_RASQ^{-1} r,  z = y + Q_0 (r - S_hat y),
+    and combine == "additive" adds the two, z = Q_0 r + S_RASQ^{-1} r.
     """
     if p.coarse == 0:
         return rasq(p, r)
+    if p.combine == "fine_first":
+        y = rasq(p, r)
+        return y + coarse_correction(p, r - apply_S_hat(p, y))
+    if p.combine == "additive":
+        return coarse_correction(p, r) + rasq(p, r)
     c = coarse_correction(p, r)
     return c + rasq(p, r - apply_S_hat(p, c))
 

@@ -16,6 +16,13 @@ Readings where the paper is silent (all listed in the design notes):
     the paper's example {1,2,3},{3,4,5,6},{6,7,8,9} for nt=9, N_D=3 (Sec. 3).
   * the boolean partition of unity D_s gives each node to the subdomain whose own
     time steps end there: s owns (s-1)k+1 .. sk.
+
+Variants of the method (ablations; the defaults are the paper's method):
+  overlap_side  "left" (paper) | "both": the overlap also extends delta nodes to the right
+  schwarz       "ras" (paper, R_s^T D_s) | "asm": additive Schwarz, R_s^T without D_s
+  local         "rasq" (Eq. (13): two sweeps) | "exact": the local inverse of Eq. (9),
+                (R_s J_hat M_u^{-1} J_hat^T R_s^T)^{-1}
+  combine       "coarse_first" (the reading of Eq. (15)) | "fine_first" | "additive"
 """
 
 from dataclasses import dataclass
@@ -35,6 +42,10 @@ class Problem:
     n_sub: int = 1     # number of time subdomains N_D
     overlap: int = 1   # delta: extra time-nodes to the left of each subdomain
     coarse: int = 2    # 0: one-level RASQ; 1: constant coarse basis; 2: constant+linear (paper)
+    overlap_side: str = "left"
+    schwarz: str = "ras"
+    local: str = "rasq"
+    combine: str = "coarse_first"
 
     # ---- derived quantities -------------------------------------------------
     @property
@@ -103,13 +114,23 @@ class Problem:
             raise ValueError("coarse must be 0, 1 or 2")
         if self.coarse == 2 and self.k < 2:
             raise ValueError("a linear coarse basis needs at least 2 time steps per subdomain")
+        if self.overlap_side not in ("left", "both"):
+            raise ValueError("overlap_side must be 'left' or 'both'")
+        if self.schwarz not in ("ras", "asm"):
+            raise ValueError("schwarz must be 'ras' or 'asm'")
+        if self.local not in ("rasq", "exact"):
+            raise ValueError("local must be 'rasq' or 'exact'")
+        if self.combine not in ("coarse_first", "fine_first", "additive"):
+            raise ValueError("combine must be 'coarse_first', 'fine_first' or 'additive'")
         return self
 
 
 def subdomain_nodes(p: Problem, s: int):
-    """Time-nodes of subdomain s (1-based), Sec. 3: its own steps plus `overlap` earlier nodes."""
+    """Time-nodes of subdomain s (1-based), Sec. 3: its own steps plus `overlap` earlier nodes
+    (and, with overlap_side "both", `overlap` later nodes)."""
     first = max(1, (s - 1) * p.k + 1 - p.overlap)
-    return list(range(first, s * p.k + 1))
+    last = s * p.k if p.overlap_side == "left" else min(p.nt, s * p.k + p.overlap)
+    return list(range(first, last + 1))
 
 
 def owned_nodes(p: Problem, s: int):

@@ -396,6 +396,144 @@ def test_coarse_correction_invariant_to_linear_basis_normalisation():
                                atol=1e-10 * np.abs(want).max())
 
 
+# ---- ablation variants -------------------------------------------------------------------------
+
+def test_symmetric_overlap_node_sets():
+    """overlap_side "both" extends each subdomain delta nodes to the right as well (clipped to
+    1..nt); the owned sets stay the same and still partition the nodes."""
+    p = Problem(nx=3, ny=3, nt=9, n_sub=3, overlap=1, coarse=1, overlap_side="both").validate()
+    assert [subdomain_nodes(p, s) for s in (1, 2, 3)] == [[1, 2, 3, 4], [3, 4, 5, 6, 7], [6, 7, 8, 9]]
+    for nt, nd, ov in [(32, 4, 2), (20, 5, 4), (16, 16, 1)]:
+        p = Problem(nx=3, ny=3, nt=nt, n_sub=nd, overlap=ov, coarse=1, overlap_side="both").validate()
+        assert sorted(n for s in range(1, nd + 1) for n in owned_nodes(p, s)) == list(range(1, nt + 1))
+        for s in range(1, nd + 1):
+            assert set(owned_nodes(p, s)) <= set(subdomain_nodes(p, s))
+
+
+def _dense_one_level(p, r):
+    """sum_s R_s^T E_s (local inverse) R_s r assembled from dense matrices: local inverse
+    J_N^{-T} h J_N^{-1} (RASQ) or (R_s S_hat R_s^T)^{-1} (Eq. (9)); E_s = D_s (RAS) or I (ASM)."""
+    nxy = p.mx * p.my
+    Jh = dr.dense_J(p, p.sigma)
+    Sh = dr.dense_schur_hat(p)
+    out = np.zeros(p.field_shape)
+    for s in range(1, p.n_sub + 1):
+        nodes = subdomain_nodes(p, s)
+        idx = np.concatenate([np.arange((n - 1) * nxy, n * nxy) for n in nodes])
+        rl = r.reshape(-1)[idx]
+        if p.local == "rasq":
+            JN = Jh[np.ix_(idx, idx)]
+            xl = np.linalg.solve(JN.T, p.h * np.linalg.solve(JN, rl))
+        else:
+            xl = np.linalg.solve(Sh[np.ix_(idx, idx)], rl)
+        keep = owned_nodes(p, s) if p.schwarz == "ras" else nodes
+        for i, n in enumerate(nodes):
+            if n in keep:
+                out[n - 1] += xl[i * nxy:(i + 1) * nxy].reshape(p.slice_shape)
+    return out
+
+
+@pytest.mark.parametrize("side", ["left", "both"])
+@pytest.mark.parametrize("schwarz", ["ras", "asm"])
+@pytest.mark.parametrize("local", ["rasq", "exact"])
+def test_one_level_variants_match_dense_assembly(side, schwarz, local):
+    p = _tiny(nt=12, n_sub=4, overlap=2, coarse=0, overlap_side=side, schwarz=schwarz, local=local)
+    r = np.random.default_rng(30).standard_normal(p.field_shape)
+    want = _dense_one_level(p, r)
+    np.testing.assert_allclose(pc.rasq(p, r), want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+
+
+def test_exact_local_operator_differs_from_rasq_by_the_earlier_step():
+    """R_s S_hat R_s^T - (1/h) J_N J_N^T = (1/h) e_1 e_1^T (x) I when the subdomain starts after
+    node 1 (the coupling to the step before it), and 0 when it starts at node 1."""
+    p = _tiny(nt=12, n_sub=4, overlap=1, coarse=0)
+    nxy = p.mx * p.my
+    Jh = dr.dense_J(p, p.sigma)
+    Sh = dr.dense_schur_hat(p)
+    for s in range(1, p.n_sub + 1):
+        nodes = subdomain_nodes(p, s)
+        idx = np.concatenate([np.arange((n - 1) * nxy, n * nxy) for n in nodes])
+        JN = Jh[np.ix_(idx, idx)]
+        diff = Sh[np.ix_(idx, idx)] - JN @ JN.T / p.h
+        want = np.zeros_like(diff)
+        if nodes[0] >= 2:
+            want[:nxy, :nxy] = np.eye(nxy) / p.h
+        np.testing.assert_allclose(diff, want, atol=1e-9 * np.abs(Sh).max())
+
+
+def test_single_subdomain_exact_local_is_exact():
+    p = _tiny(n_sub=1, overlap=0, coarse=0, local="exact")
+    r = np.random.default_rng(31).standard_normal(p.field_shape)
+    z = pc.schur_inverse(p, r)
+    np.testing.assert_allclose(dr.dense_schur_hat(p) @ z.reshape(-1), r.reshape(-1), rtol=1e-9,
+                               atol=1e-9 * np.abs(r).max())
+
+
+def _operator_matrix(p, fn):
+    n = int(np.prod(p.field_shape))
+    M = np.zeros((n, n))
+    for c in range(n):
+        e = np.zeros(n)
+        e[c] = 1.0
+        M[:, c] = fn(e.reshape(p.field_shape)).reshape(-1)
+    return M
+
+
+def test_asm_is_symmetric_positive_definite_and_ras_is_not_symmetric():
+    base = dict(nx=4, ny=3, nt=8, n_sub=4, overlap=1, coarse=0)
+    pa = _tiny(**base, schwarz="asm")
+    Ma = _operator_matrix(pa, lambda v: pc.rasq(pa, v))
+    assert np.abs(Ma - Ma.T).max() <= 1e-10 * np.abs(Ma).max()
+    assert np.linalg.eigvalsh(0.5 * (Ma + Ma.T)).min() > 0
+    pr = _tiny(**base)
+    Mr = _operator_matrix(pr, lambda v: pc.rasq(pr, v))
+    assert np.abs(Mr - Mr.T).max() > 1e-3 * np.abs(Mr).max()
+
+
+@pytest.mark.parametrize("combine", ["coarse_first", "fine_first", "additive"])
+def test_two_level_combinations_match_their_error_propagators(combine):
+    """With M the one-level operator and Q_0 = Z (Z^T S_hat Z)^{-1} Z^T assembled densely:
+    coarse first  I - P S_hat = (I - M S_hat)(I - Q_0 S_hat);
+    fine first    I - P S_hat = (I - Q_0 S_hat)(I - M S_hat);
+    additive      P = Q_0 + M."""
+    base = dict(nx=4, ny=3, nt=8, n_sub=4, overlap=1, coarse=2)
+    p = _tiny(**base, combine=combine)
+    p1 = _tiny(**dict(base, coarse=0))
+    M = _operator_matrix(p1, lambda v: pc.rasq(p1, v))
+    P = _operator_matrix(p, lambda v: pc.schur_inverse(p, v))
+    Z, Sh = _dense_coarse(p, pc.coarse_time_basis(p))
+    Q0 = Z @ np.linalg.solve(Z.T @ Sh @ Z, Z.T)
+    I = np.eye(Sh.shape[0])
+    if combine == "coarse_first":
+        want = I - (I - M @ Sh) @ (I - Q0 @ Sh)
+        got = P @ Sh
+    elif combine == "fine_first":
+        want = I - (I - Q0 @ Sh) @ (I - M @ Sh)
+        got = P @ Sh
+    else:
+        want, got = Q0 + M, P
+    np.testing.assert_allclose(got, want, atol=1e-9 * np.abs(want).max())
+
+
+def test_fine_first_leaves_a_residual_orthogonal_to_the_coarse_space():
+    p = _tiny(nt=12, n_sub=4, overlap=2, coarse=2, combine="fine_first")
+    Z, Sh = _dense_coarse(p, pc.coarse_time_basis(p))
+    r = np.random.default_rng(32).standard_normal(p.field_shape)
+    resid = r.reshape(-1) - Sh @ pc.schur_inverse(p, r).reshape(-1)
+    assert np.abs(Z.T @ resid).max() < 1e-9 * np.abs(Z.T @ r.reshape(-1)).max()
+
+
+@pytest.mark.parametrize("variant", [dict(overlap_side="both"), dict(schwarz="asm"), dict(local="exact"),
+                                     dict(combine="fine_first"), dict(combine="additive")])
+def test_variant_preconditioned_gmres_reaches_dense_solution(variant):
+    p = _tiny(nt=8, n_sub=4, overlap=1, coarse=2, **variant)
+    rng = np.random.default_rng(33)
+    f = op.rhs(p, rng.standard_normal(p.slice_shape), rng.standard_normal(p.field_shape))
+    xd = dr.dense_solve(p, f)
+    res = gm.gmres(lambda v: op.apply_K(p, v), lambda v: pc.apply_Pinv(p, v), f, restart=40, maxit=200, rtol=1e-12)
+    assert res.converged and np.abs(res.x - xd).max() <= 1e-8 * np.abs(xd).max()
+
+
 # ---- the whole iteration ---------------------------------------------------------------------
 
 @pytest.mark.parametrize("coarse,overlap", [(2, 1), (2, 2), (1, 1), (0, 1), (0, 0)])
