@@ -87,7 +87,25 @@ typedef struct kktdd_problem {
   int32_t coarse;     /* 0: one-level RASQ; 1: constant coarse basis; 2: constant+linear   */
   int32_t precision;  /* enum kktdd_precision                                              */
   int32_t sweep;      /* enum kktdd_sweep                                                  */
+  /* Variants of the method for ablation studies (0 = the paper's method in every field).
+   * Any nonzero variant needs sweep = KKTDD_SWEEP_MODAL and precision = KKTDD_FP64. */
+  int32_t overlap_side; /* enum kktdd_overlap_side                                         */
+  int32_t schwarz;      /* enum kktdd_schwarz                                              */
+  int32_t local;        /* enum kktdd_local                                                */
+  int32_t combine;      /* enum kktdd_combine                                              */
 } kktdd_problem;
+
+/* Subdomain extent (Sec. 3): delta nodes to the left (the paper's example), or to both sides. */
+enum kktdd_overlap_side { KKTDD_OVERLAP_LEFT = 0, KKTDD_OVERLAP_BOTH = 1 };
+/* Schwarz sum (Eqs. (9), (13)): restricted (R_s^T D_s, the paper) or additive (R_s^T). */
+enum kktdd_schwarz { KKTDD_SCHWARZ_RAS = 0, KKTDD_SCHWARZ_ASM = 1 };
+/* Local operator: the two sweeps of Eq. (13) (RASQ, the paper) or the exact local inverse
+ * (R_s J_hat M_u^{-1} J_hat^T R_s^T)^{-1} of Eq. (9). */
+enum kktdd_local { KKTDD_LOCAL_RASQ = 0, KKTDD_LOCAL_EXACT = 1 };
+/* Two-level combination (Eq. (15)): coarse level first, then the fine level on the remaining
+ * residual (the default reading); fine level first; or the sum of both. */
+enum kktdd_combine { KKTDD_COMBINE_COARSE_FIRST = 0, KKTDD_COMBINE_FINE_FIRST = 1,
+                     KKTDD_COMBINE_ADDITIVE = 2 };
 
 typedef struct kktdd_stats {
   int32_t iters;          /* Arnoldi steps over all cycles                                 */

@@ -20,6 +20,13 @@ PRECISION_NAMES = {v: k for k, v in PRECISIONS.items()}
 # enum kktdd_sweep
 SWEEP_STEP, SWEEP_MODAL = 0, 1
 SWEEPS = {"step": SWEEP_STEP, "modal": SWEEP_MODAL}
+# variants of the method (ablations); the first value of each is the paper's method
+VARIANTS = {
+    "overlap_side": {"left": 0, "both": 1},
+    "schwarz": {"ras": 0, "asm": 1},
+    "local": {"rasq": 0, "exact": 1},
+    "combine": {"coarse_first": 0, "fine_first": 1, "additive": 2},
+}
 # longest Arnoldi cycle of fgmres_solve
 MAX_RESTART = 1024
 
@@ -38,7 +45,9 @@ class Problem(ctypes.Structure):
                 ("nt", ctypes.c_int32), ("T", ctypes.c_double),
                 ("nu", ctypes.c_double), ("omega", ctypes.c_double),
                 ("n_sub", ctypes.c_int32), ("overlap", ctypes.c_int32),
-                ("coarse", ctypes.c_int32), ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32)]
+                ("coarse", ctypes.c_int32), ("precision", ctypes.c_int32), ("sweep", ctypes.c_int32),
+                ("overlap_side", ctypes.c_int32), ("schwarz", ctypes.c_int32),
+                ("local", ctypes.c_int32), ("combine", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -98,14 +107,16 @@ def load():
 
 
 def make_problem(params, precision="fp64", sweep="step"):
-    """Problem struct from a parameter dict (keys nx, ny, nt, Lx, Ly, T, nu, omega, n_sub, overlap, coarse)."""
+    """Problem struct from a parameter dict (keys nx, ny, nt, Lx, Ly, T, nu, omega, n_sub, overlap,
+    coarse, and optionally the variant keys overlap_side, schwarz, local, combine)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     swp = SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
     return Problem(int(params["nx"]), int(params["ny"]), float(params.get("Lx", 1.0)),
                    float(params.get("Ly", 1.0)), int(params["nt"]), float(params.get("T", 1.0)),
                    float(params.get("nu", 1.0)), float(params.get("omega", 1e-2)),
                    int(params.get("n_sub", 1)), int(params.get("overlap", 1)),
-                   int(params.get("coarse", 2)), prec, swp)
+                   int(params.get("coarse", 2)), prec, swp,
+                   *[VARIANTS[key][params.get(key, next(iter(VARIANTS[key])))] for key in VARIANTS])
 
 
 class KKTDDError(RuntimeError):

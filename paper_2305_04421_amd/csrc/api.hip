@@ -117,6 +117,7 @@ struct kktdd_handle {
   // modal (transform-hoisted) sweeps
   void *Rhat = nullptr, *Mtmp = nullptr;
   double* Ysc = nullptr;
+  double* ext = nullptr;                       // additive-Schwarz extension values
   // coarse
   double *r0 = nullptr, *c0 = nullptr, *Dc0 = nullptr, *DDc0 = nullptr;
   double *chat = nullptr, *ctmp = nullptr, *cfac = nullptr;
@@ -190,12 +191,19 @@ int validate(const kktdd_problem* p) {
   for (double v : pos)
     if (!(v > 0.0) || !std::isfinite(v)) return bad("Lx, Ly, T, nu, omega must be positive and finite");
   if (p->n_sub < 1 || p->nt % p->n_sub != 0) return bad("n_sub must be >= 1 and divide nt");
+  if (p->n_sub > 65535) return bad("n_sub must be <= 65535 (one launch row per subdomain)");
   const int k = p->nt / p->n_sub;
   if (p->overlap < 0 || p->overlap > k) return bad("overlap must satisfy 0 <= overlap <= nt/n_sub");
   if (p->coarse < 0 || p->coarse > 2) return bad("coarse must be 0, 1 or 2");
   if (p->coarse == 2 && k < 2) return bad("a linear coarse basis needs nt/n_sub >= 2");
   if (p->precision < KKTDD_FP64 || p->precision > KKTDD_AUTO) return bad("unknown precision");
   if (p->sweep != KKTDD_SWEEP_STEP && p->sweep != KKTDD_SWEEP_MODAL) return bad("unknown sweep placement");
+  if (p->overlap_side < 0 || p->overlap_side > 1 || p->schwarz < 0 || p->schwarz > 1 ||
+      p->local < 0 || p->local > 1 || p->combine < 0 || p->combine > 2)
+    return bad("unknown method variant");
+  if ((p->overlap_side || p->schwarz || p->local || p->combine) &&
+      (p->sweep != KKTDD_SWEEP_MODAL || (p->precision != KKTDD_FP64 && p->precision != KKTDD_AUTO)))
+    return bad("method variants run on the float64 modal sweeps only");
   if ((long long)p->nt * (p->nx - 1) * (p->ny - 1) > (1LL << 40)) return bad("problem too large");
   return KKTDD_OK;
 }
@@ -224,7 +232,9 @@ constexpr double kAutoKappaFp32 = 500.0;
 
 kktdd_problem resolve(const kktdd_problem& p) {
   kktdd_problem r = p;
-  if (r.precision == KKTDD_AUTO) r.precision = kappa_D(p) <= kAutoKappaFp32 ? KKTDD_FP32 : KKTDD_FP64;
+  const bool variant = p.overlap_side || p.schwarz || p.local || p.combine;
+  if (r.precision == KKTDD_AUTO)
+    r.precision = !variant && kappa_D(p) <= kAutoKappaFp32 ? KKTDD_FP32 : KKTDD_FP64;
   return r;
 }
 
@@ -247,7 +257,11 @@ Geom make_geom(const kktdd_problem& p) {
   g.nd = p.n_sub;
   g.k = p.nt / p.n_sub;
   g.delta = p.overlap;
-  g.L = g.k + g.delta;
+  g.sym = p.overlap_side;
+  g.asm_sum = p.schwarz;
+  g.exact_local = p.local;
+  g.combine = p.combine;
+  g.L = g.k + g.delta * (1 + g.sym);
   g.nb = p.coarse;
   g.nc = g.nb * g.nd;
   return g;
@@ -298,6 +312,18 @@ bool needs_rprime(const Geom& g, int precision, int sweep) {
   return sweep == KKTDD_SWEEP_STEP || physical_coarse(g, precision, sweep);
 }
 
+// Modal sweep store (doubles): the forward states when a sweep is too long for registers, or
+// the pivots and forward values of the exact local solves.
+size_t modal_store(const Geom& g) {
+  const size_t per = (size_t)g.nd * g.L * (size_t)g.padded();
+  if (g.exact_local) return 2 * per;
+  return g.L > kModalRegSteps ? per : 0;
+}
+// Additive-Schwarz extension values (doubles): delta nodes per side and subdomain.
+size_t modal_ext(const Geom& g) {
+  return g.asm_sum ? (size_t)g.nd * g.delta * (1 + g.sym) * (size_t)g.padded() : 0;
+}
+
 Plan plan(const Geom& g, int precision, int sweep, int R) {
   const size_t el = precision == KKTDD_FP64 ? 8 : 4;
   const size_t MM = (size_t)g.padded();
@@ -305,8 +331,7 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
   p.tables = ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My + MM) * 12 + (size_t)(g.mx + g.my) * 8;
   if (is_bf16(precision)) p.tables += ((size_t)g.Mx * g.Mx + (size_t)g.My * g.My) * 6;
   if (sweep == KKTDD_SWEEP_MODAL) {
-    p.sweeps = 2 * (size_t)g.nt * MM * el;
-    if (g.L > kModalRegSteps) p.sweeps += (size_t)g.nd * g.L * MM * 8;
+    p.sweeps = 2 * (size_t)g.nt * MM * el + (modal_store(g) + modal_ext(g)) * 8;
   } else {
     p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el;
   }
@@ -498,17 +523,34 @@ int schur_apply_modal(kktdd_handle* H, const double* rw, const double* dscale, d
     const double* c0 = nullptr;
     if (int e = coarse_physical(H, rw, dscale, &c0)) return e;
     if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), H->rprime, nullptr, H->Mtmp, H->Rhat, g.nt, s)) return e;
-    if (int e = launch_modal_sweeps(g, prec, H->Rhat, nullptr, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
+    if (int e = launch_modal_sweeps(g, prec, H->Rhat, nullptr, 0, H->lamx, H->lamy, H->Ysc, H->Mtmp,
+                                    nullptr, s)) return e;
     return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, c0, s);
   }
+  // float64: everything in sine-mode space between one forward and one inverse transform
+  double* rhat = static_cast<double*>(H->Rhat);
+  double* zhat = static_cast<double*>(H->Mtmp);
   if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), rw, dscale, H->Mtmp, H->Rhat, g.nt, s)) return e;
+  const bool coarse = g.nb > 0;
+  const bool fine_first = coarse && g.combine == KKTDD_COMBINE_FINE_FIRST;
   const double* c0 = nullptr;
-  if (g.nb > 0) {
-    if (int e = launch_modal_restrict(g, prec, H->Rhat, H->chat, s)) return e;
+  if (coarse && !fine_first) {
+    if (int e = launch_modal_restrict(g, prec, rhat, H->chat, s)) return e;
     if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
     c0 = H->chat;
   }
-  if (int e = launch_modal_sweeps(g, prec, H->Rhat, c0, H->lamx, H->lamy, H->Ysc, H->Mtmp, s)) return e;
+  // coarse first: the sweeps see r - S_hat c; additive: r itself; both add c to the output
+  const int sub = g.combine == KKTDD_COMBINE_COARSE_FIRST ? 1 : 0;
+  if (int e = launch_modal_sweeps(g, prec, rhat, c0, sub, H->lamx, H->lamy, H->Ysc, zhat, H->ext, s)) return e;
+  if (g.asm_sum)
+    if (int e = launch_modal_asm_add(g, H->ext, zhat, s)) return e;
+  if (fine_first) {
+    // y = fine level of r; z = y + Q_0 (r - S_hat y)
+    if (int e = launch_modal_residual(g, zhat, H->lamx, H->lamy, rhat, s)) return e;
+    if (int e = launch_modal_restrict(g, prec, rhat, H->chat, s)) return e;
+    if (int e = launch_coarse_solve(g, H->cfac, H->chat, s)) return e;
+    if (int e = launch_modal_prolong_add(g, H->chat, zhat, s)) return e;
+  }
   return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, nullptr, s);
 }
 
@@ -640,8 +682,8 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     if (int e = dalloc(H, &mt, (size_t)g.nt * MM * el)) return fail(e);
     H->Rhat = rh;
     H->Mtmp = mt;
-    if (g.L > kModalRegSteps)
-      if (int e = dalloc(H, &H->Ysc, (size_t)g.nd * g.L * MM)) return fail(e);
+    if (int e = dalloc(H, &H->Ysc, modal_store(g))) return fail(e);
+    if (int e = dalloc(H, &H->ext, modal_ext(g))) return fail(e);
   } else {
     unsigned char *t, *u, *y;
     if (int e = dalloc(H, &t, (size_t)g.nd * MM * el)) return fail(e);

@@ -28,7 +28,12 @@ struct Geom {
   double omega, dt;
   double sigma;        // 1 + dt/sqrt(omega): J_hat's diagonal shift
   int nd, k, delta;    // time subdomains, steps per subdomain, overlap
-  int L;               // sweep length k + delta (subdomain 1 padded with zero nodes)
+  int L;               // sweep length k + delta (+ delta with overlap on both sides);
+                       // subdomain 1 is padded with zero nodes in front
+  int sym;             // overlap on both sides (enum kktdd_overlap_side)
+  int asm_sum;         // additive Schwarz sum (enum kktdd_schwarz)
+  int exact_local;     // exact local inverse of Eq. (9) (enum kktdd_local)
+  int combine;         // two-level combination (enum kktdd_combine)
   int nb;              // coarse basis functions per subdomain (0, 1, 2)
   int nc;              // nb*nd coarse slots per point
   __host__ __device__ long long padded() const { return (long long)Mx * My; }
@@ -107,8 +112,12 @@ int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void*
 int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
                           hipStream_t s);
 int launch_modal_sweeps(const Geom& g, int precision, const void* rhat, const double* c0,
-                        const double* lamx, const double* lamy, double* yscratch, void* zhat,
-                        hipStream_t s);
+                        int sub_coarse, const double* lamx, const double* lamy, double* yscratch,
+                        void* zhat, double* ext, hipStream_t s);
+int launch_modal_asm_add(const Geom& g, const double* ext, double* zhat, hipStream_t s);
+int launch_modal_residual(const Geom& g, const double* zhat, const double* lamx,
+                          const double* lamy, double* rhat, hipStream_t s);
+int launch_modal_prolong_add(const Geom& g, const double* c0, double* zhat, hipStream_t s);
 
 // ---- coarse.hip: Nicolaides coarse level --------------------------------------------------
 int launch_restrict(const Geom& g, const double* rw, const double* dscale, double* r0,

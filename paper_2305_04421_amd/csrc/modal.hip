@@ -13,6 +13,16 @@
 //     output     z_hat^n = c_hat^n + x^n on owned nodes
 // and z = (4/(nx ny)) S_y z_hat S_x (one batched GEMM pair).  The result equals the per-step
 // sweeps up to rounding; only the placement of the transforms differs.
+//
+// The variants of the method (ablations) run here, in float64:
+//   overlap on both sides   the sweep also covers delta nodes after the owned ones
+//   additive Schwarz        non-owned outputs go to extension slots and are added to
+//                           their owners by a second kernel (fixed order)
+//   exact local inverse     Eq. (9): the restricted tridiagonal (1/h) T solved by LDL^T per
+//                           mode instead of the two sweeps
+//   fine first / additive   two-level combinations other than coarse first: the sweeps see
+//                           r itself; fine first then forms r - S_hat y in mode space,
+//                           restricts, solves and adds the prolonged correction
 #include "internal.h"
 
 namespace kktdd {
@@ -55,43 +65,82 @@ __device__ inline double chat_at(const Geom& g, const double* __restrict__ c0, l
   return v;
 }
 
+// Node ranges of subdomain s (0-based): owned nodes s*k+1 .. (s+1)*k; the sweep covers
+// first .. last, first = s*k+1-delta (slot 0 of the forward store), last = (s+1)*k
+// (+ delta with overlap on both sides), both clipped to 1..nt.  Nodes left of the owned
+// range map to extension slots 0..delta-1, nodes right of it to slots delta..2*delta-1.
+struct Range {
+  int own_lo, own_hi, first, lo, hi;
+};
+__device__ inline Range node_range(const Geom& g, int s) {
+  Range r;
+  r.own_lo = s * g.k + 1;
+  r.own_hi = (s + 1) * g.k;
+  r.first = r.own_lo - g.delta;
+  r.lo = r.first < 1 ? 1 : r.first;
+  const int last = r.own_hi + (g.sym ? g.delta : 0);
+  r.hi = last > g.nt ? g.nt : last;
+  return r;
+}
+
+// r'_n of one mode: r_hat_n, minus (S_hat c_hat)_n / h when the coarse correction comes first
+//   (S_hat c)^n = (1/h) ((d^2 + [n>=2]) c^n - d c^{n-1} [n>=2] - d c^{n+1})
+template <typename T>
+__device__ inline double rprime_at(const Geom& g, const T* __restrict__ rhat,
+                                   const double* __restrict__ c0, int sub, double d, long long MM,
+                                   long long m, int n) {
+  double r = (double)rhat[(long long)(n - 1) * MM + m];
+  if (c0 && sub) {
+    const double cn = chat_at(g, c0, MM, m, n);
+    double sc = d * d * cn - d * chat_at(g, c0, MM, m, n + 1);
+    if (n >= 2) sc += cn - d * chat_at(g, c0, MM, m, n - 1);
+    r -= sc / g.h;
+  }
+  return r;
+}
+
+// Output of node n of subdomain s: owned nodes get c_hat + x, the others (additive Schwarz)
+// go to the extension slots, which a second kernel adds to their owners.
+template <typename T>
+__device__ inline void put_out(const Geom& g, const Range& rg, const double* __restrict__ c0,
+                               long long MM, long long m, int s, int n, double x,
+                               T* __restrict__ zhat, double* __restrict__ ext) {
+  if (n >= rg.own_lo && n <= rg.own_hi) {
+    const double c = c0 ? chat_at(g, c0, MM, m, n) : 0.0;
+    zhat[(long long)(n - 1) * MM + m] = (T)(c + x);
+  } else if (ext) {
+    const int E = g.delta * (1 + g.sym);
+    const int slot = n < rg.own_lo ? n - rg.first : g.delta + (n - rg.own_hi - 1);
+    ext[((long long)s * E + slot) * MM + m] = x;
+  }
+}
+
 // One thread = one sine mode of one subdomain: residual, forward sweep, adjoint sweep,
-// owned-node output.  Padded modes write zeros.
+// output.  Padded modes write zeros on their owned nodes.
 template <typename T, bool REG>
 __global__ void __launch_bounds__(kBlock)
-k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
+k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0, int sub,
               const double* __restrict__ lamx, const double* __restrict__ lamy,
-              double* __restrict__ yscratch, T* __restrict__ zhat) {
+              double* __restrict__ yscratch, T* __restrict__ zhat, double* __restrict__ ext) {
   const long long MM = g.padded();
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int s = blockIdx.y;
   if (m >= MM) return;
   const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
-  const int first = s * g.k + 1 - g.delta;
+  const Range rg = node_range(g, s);
   if (q >= g.my || p >= g.mx) {
-    for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) zhat[(long long)(n - 1) * MM + m] = (T)0;
+    for (int n = rg.own_lo; n <= rg.own_hi; ++n) zhat[(long long)(n - 1) * MM + m] = (T)0;
     return;
   }
   const double d = g.sigma + lamy[q] + lamx[p];
-  const double invd = 1.0 / d, invh = 1.0 / g.h;
+  const double invd = 1.0 / d;
   double yreg[REG ? kRegSteps : 1];
   double* ysc = REG ? nullptr : yscratch + ((long long)s * g.L) * MM + m;
-  // forward sweep over the subdomain's nodes (zero right-hand side below node 1)
+  // forward sweep over the subdomain's nodes (zero state before the first)
   double y = 0.0;
-  for (int j = 0; j < g.L; ++j) {
-    const int n = first + j;
-    double r = 0.0;
-    if (n >= 1) {
-      r = (double)rhat[(long long)(n - 1) * MM + m];
-      if (c0) {
-        // (S_hat c)^n = (1/h) ((d^2 + [n>=2]) c^n - d c^{n-1} [n>=2] - d c^{n+1})
-        const double cn = chat_at(g, c0, MM, m, n);
-        double sc = d * d * cn - d * chat_at(g, c0, MM, m, n + 1);
-        if (n >= 2) sc += cn - d * chat_at(g, c0, MM, m, n - 1);
-        r -= sc * invh;
-      }
-    }
-    y = (r + y) * invd;
+  for (int n = rg.lo; n <= rg.hi; ++n) {
+    y = (rprime_at(g, rhat, c0, sub, d, MM, m, n) + y) * invd;
+    const int j = n - rg.first;
     if (REG) {
 #pragma unroll
       for (int i = 0; i < kRegSteps; ++i)
@@ -100,9 +149,10 @@ k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
       ysc[(long long)j * MM] = y;
     }
   }
-  // adjoint sweep with the mass scale, output on owned nodes
+  // adjoint sweep with the mass scale (zero state after the last node)
   double x = 0.0;
-  for (int j = g.L - 1; j >= 0; --j) {
+  for (int n = rg.hi; n >= rg.lo; --n) {
+    const int j = n - rg.first;
     double yj = 0.0;
     if (REG) {
 #pragma unroll
@@ -112,26 +162,130 @@ k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
       yj = ysc[(long long)j * MM];
     }
     x = (g.h * yj + x) * invd;
-    if (j >= g.delta) {
-      const int n = first + j;
-      const double c = c0 ? chat_at(g, c0, MM, m, n) : 0.0;
-      zhat[(long long)(n - 1) * MM + m] = (T)(c + x);
-    }
+    put_out(g, rg, c0, MM, m, s, n, x, zhat, ext);
   }
 }
 
+// Exact local inverse of Eq. (9) for one sine mode of one subdomain: the restricted system
+// (1/h) T x = r' with T tridiagonal, T_nn = d^2 + [n>=2], T_{n,n+-1} = -d, solved by its
+// LDL^T factorisation (forward elimination, then back substitution).  The store holds
+// y_n / D_n and the multiplier -d / D_n of every node.
+__global__ void __launch_bounds__(kBlock)
+k_modal_exact(Geom g, const double* __restrict__ rhat, const double* __restrict__ c0, int sub,
+              const double* __restrict__ lamx, const double* __restrict__ lamy,
+              double* __restrict__ store, double* __restrict__ zhat, double* __restrict__ ext) {
+  const long long MM = g.padded();
+  const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int s = blockIdx.y;
+  if (m >= MM) return;
+  const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
+  const Range rg = node_range(g, s);
+  if (q >= g.my || p >= g.mx) {
+    for (int n = rg.own_lo; n <= rg.own_hi; ++n) zhat[(long long)(n - 1) * MM + m] = 0.0;
+    return;
+  }
+  const double d = g.sigma + lamy[q] + lamx[p];
+  const double e = -d;
+  double* zs = store + ((long long)s * g.L) * MM + m;
+  double* ls = store + ((long long)(g.nd + s) * g.L) * MM + m;
+  double Dprev = 0.0, yprev = 0.0;
+  for (int n = rg.lo; n <= rg.hi; ++n) {
+    const double a = d * d + (n >= 2 ? 1.0 : 0.0);
+    const double b = g.h * rprime_at(g, rhat, c0, sub, d, MM, m, n);
+    double Dn, yn;
+    if (n == rg.lo) {
+      Dn = a;
+      yn = b;
+    } else {
+      const double l = e / Dprev;
+      Dn = a - l * e;
+      yn = b - l * yprev;
+    }
+    const int j = n - rg.first;
+    zs[(long long)j * MM] = yn / Dn;
+    ls[(long long)j * MM] = e / Dn;
+    Dprev = Dn;
+    yprev = yn;
+  }
+  double x = 0.0;
+  for (int n = rg.hi; n >= rg.lo; --n) {
+    const int j = n - rg.first;
+    x = zs[(long long)j * MM] - (n < rg.hi ? ls[(long long)j * MM] * x : 0.0);
+    put_out(g, rg, c0, MM, m, s, n, x, zhat, ext);
+  }
+}
+
+// Additive Schwarz: add the extension values of the neighbours to the owned nodes of s
+// (left extension of s+1, then right extension of s-1), one thread per mode and subdomain.
+__global__ void __launch_bounds__(kBlock)
+k_modal_asm_add(Geom g, const double* __restrict__ ext, double* __restrict__ zhat) {
+  const long long MM = g.padded();
+  const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int s = blockIdx.y;
+  if (m >= MM) return;
+  if ((int)(m / g.Mx) >= g.my || (int)(m % g.Mx) >= g.mx) return;
+  const int E = g.delta * (1 + g.sym);
+  if (s + 1 < g.nd)
+    for (int i = 0; i < g.delta; ++i) {
+      const int n = (s + 1) * g.k + 1 - g.delta + i;
+      zhat[(long long)(n - 1) * MM + m] += ext[((long long)(s + 1) * E + i) * MM + m];
+    }
+  if (g.sym && s > 0)
+    for (int i = 0; i < g.delta; ++i) {
+      const int n = s * g.k + 1 + i;
+      zhat[(long long)(n - 1) * MM + m] += ext[((long long)(s - 1) * E + g.delta + i) * MM + m];
+    }
+}
+
+// r_hat <- r_hat - S_hat z_hat over all nodes, one thread per mode (fine level first).
+__global__ void __launch_bounds__(kBlock)
+k_modal_residual(Geom g, const double* __restrict__ zhat, const double* __restrict__ lamx,
+                 const double* __restrict__ lamy, double* __restrict__ rhat) {
+  const long long MM = g.padded();
+  const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (m >= MM) return;
+  const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
+  if (q >= g.my || p >= g.mx) return;
+  const double d = g.sigma + lamy[q] + lamx[p];
+  double zp = 0.0, zc = zhat[m];
+  for (int n = 1; n <= g.nt; ++n) {
+    const double zn = n < g.nt ? zhat[(long long)n * MM + m] : 0.0;
+    double sc = d * d * zc - d * zn;
+    if (n >= 2) sc += zc - d * zp;
+    rhat[(long long)(n - 1) * MM + m] -= sc / g.h;
+    zp = zc;
+    zc = zn;
+  }
+}
+
+// z_hat <- z_hat + Z c0 (prolongation of the coarse solution), one thread per mode.
+__global__ void __launch_bounds__(kBlock)
+k_modal_prolong_add(Geom g, const double* __restrict__ c0, double* __restrict__ zhat) {
+  const long long MM = g.padded();
+  const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (m >= MM) return;
+  if ((int)(m / g.Mx) >= g.my || (int)(m % g.Mx) >= g.mx) return;
+  for (int n = 1; n <= g.nt; ++n) zhat[(long long)(n - 1) * MM + m] += chat_at(g, c0, MM, m, n);
+}
+
 template <typename T>
-int modal_t(const Geom& g, const void* rhat, const double* c0, const double* lamx,
-            const double* lamy, double* yscratch, void* zhat, hipStream_t s) {
+int modal_t(const Geom& g, const void* rhat, const double* c0, int sub, const double* lamx,
+            const double* lamy, double* yscratch, void* zhat, double* ext, hipStream_t s) {
   const long long MM = g.padded();
   const dim3 grid((unsigned)((MM + kBlock - 1) / kBlock), g.nd);
   prof_begin(KKTDD_K_COARSE, s);
-  if (g.L <= kRegSteps)
+  if (g.exact_local)
+    hipLaunchKernelGGL(k_modal_exact, grid, dim3(kBlock), 0, s, g,
+                       static_cast<const double*>(rhat), c0, sub, lamx, lamy, yscratch,
+                       static_cast<double*>(zhat), ext);
+  else if (g.L <= kRegSteps)
     hipLaunchKernelGGL((k_modal_sweep<T, true>), grid, dim3(kBlock), 0, s, g,
-                       static_cast<const T*>(rhat), c0, lamx, lamy, yscratch, static_cast<T*>(zhat));
+                       static_cast<const T*>(rhat), c0, sub, lamx, lamy, yscratch,
+                       static_cast<T*>(zhat), ext);
   else
     hipLaunchKernelGGL((k_modal_sweep<T, false>), grid, dim3(kBlock), 0, s, g,
-                       static_cast<const T*>(rhat), c0, lamx, lamy, yscratch, static_cast<T*>(zhat));
+                       static_cast<const T*>(rhat), c0, sub, lamx, lamy, yscratch,
+                       static_cast<T*>(zhat), ext);
   KKT_HIP(hipGetLastError());
   // read r_hat over the subdomain nodes, write z_hat once
   const double el = sizeof(T);
@@ -158,10 +312,45 @@ int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double
 }
 
 int launch_modal_sweeps(const Geom& g, int precision, const void* rhat, const double* c0,
-                        const double* lamx, const double* lamy, double* yscratch, void* zhat,
-                        hipStream_t s) {
-  if (precision != KKTDD_FP64) return modal_t<float>(g, rhat, c0, lamx, lamy, yscratch, zhat, s);
-  return modal_t<double>(g, rhat, c0, lamx, lamy, yscratch, zhat, s);
+                        int sub_coarse, const double* lamx, const double* lamy, double* yscratch,
+                        void* zhat, double* ext, hipStream_t s) {
+  if (g.exact_local && precision != KKTDD_FP64)
+    return set_error(KKTDD_EINVAL, "the exact local inverse runs in float64 only");
+  if (g.asm_sum && !ext) return set_error(KKTDD_EINVAL, "additive Schwarz needs its extension buffer");
+  if (precision != KKTDD_FP64)
+    return modal_t<float>(g, rhat, c0, sub_coarse, lamx, lamy, yscratch, zhat, ext, s);
+  return modal_t<double>(g, rhat, c0, sub_coarse, lamx, lamy, yscratch, zhat, ext, s);
+}
+
+int launch_modal_asm_add(const Geom& g, const double* ext, double* zhat, hipStream_t s) {
+  const long long MM = g.padded();
+  const dim3 grid((unsigned)((MM + kBlock - 1) / kBlock), g.nd);
+  prof_begin(KKTDD_K_COARSE, s);
+  hipLaunchKernelGGL(k_modal_asm_add, grid, dim3(kBlock), 0, s, g, ext, zhat);
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 24.0 * MM * g.nd * g.delta * (1 + g.sym), 0.0);
+  return 0;
+}
+
+int launch_modal_residual(const Geom& g, const double* zhat, const double* lamx,
+                          const double* lamy, double* rhat, hipStream_t s) {
+  const long long MM = g.padded();
+  prof_begin(KKTDD_K_COARSE, s);
+  hipLaunchKernelGGL(k_modal_residual, dim3((unsigned)((MM + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, g, zhat, lamx, lamy, rhat);
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 24.0 * MM * g.nt, 0.0);
+  return 0;
+}
+
+int launch_modal_prolong_add(const Geom& g, const double* c0, double* zhat, hipStream_t s) {
+  const long long MM = g.padded();
+  prof_begin(KKTDD_K_COARSE, s);
+  hipLaunchKernelGGL(k_modal_prolong_add, dim3((unsigned)((MM + kBlock - 1) / kBlock)), dim3(kBlock),
+                     0, s, g, c0, zhat);
+  KKT_HIP(hipGetLastError());
+  prof_end(KKTDD_K_COARSE, s, 16.0 * MM * g.nt + 8.0 * MM * g.nc, 0.0);
+  return 0;
 }
 
 }  // namespace kktdd

@@ -106,6 +106,36 @@ def test_auto_precision_is_accepted_and_planned_like_its_resolution(lib):
         assert memory_plan(params, "auto", 10) == memory_plan(params, want, 10)
 
 
+@pytest.mark.parametrize("bad", [dict(overlap_side="both"), dict(schwarz="asm", precision="fp32", sweep="modal"),
+                                 dict(local="exact", sweep="step"), dict(combine="additive", precision="bf16x3",
+                                                                         sweep="modal")])
+def test_variants_are_rejected_off_the_float64_modal_path(lib, bad):
+    from paper_2305_04421_amd import _lib
+    p = _prob(**bad)
+    assert lib.kkt_validate(ctypes.byref(p)) == _lib.EINVAL
+    assert b"modal" in lib.kkt_last_error()
+
+
+def test_variant_fields_out_of_range_are_rejected(lib):
+    from paper_2305_04421_amd import _lib
+    for field, value in (("overlap_side", 2), ("schwarz", -1), ("local", 2), ("combine", 3)):
+        p = _prob(sweep="modal")
+        setattr(p, field, value)
+        assert lib.kkt_validate(ctypes.byref(p)) == _lib.EINVAL, field
+
+
+def test_variant_memory_plan():
+    from paper_2305_04421_amd import memory_plan
+    base = dict(nx=32, ny=32, nt=64, n_sub=4, overlap=2, coarse=2)
+    plain = memory_plan(base, "fp64", 0, sweep="modal")
+    asm = memory_plan(dict(base, schwarz="asm", overlap_side="both"), "fp64", 0, sweep="modal")
+    exact = memory_plan(dict(base, local="exact"), "fp64", 0, sweep="modal")
+    MM = 32 * 32   # padded 31 -> 32
+    assert asm - plain == 4 * 2 * 2 * MM * 8            # extension slots: N_D * 2 delta * MM
+    assert exact - plain == 2 * 4 * (16 + 2) * MM * 8   # pivots and values: 2 * N_D * L * MM
+    assert memory_plan(dict(base, local="exact"), "auto", 0, sweep="modal") == exact
+
+
 def test_memory_plan_of_a_long_cycle(lib):
     # the unrestarted solves of the weak-scaling experiment keep up to 421 basis vectors
     p = _prob(nx=16, ny=16, nt=256, n_sub=16)
