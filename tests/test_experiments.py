@@ -38,3 +38,27 @@ def test_markdown_marks_unconverged_runs():
     assert lines[0].startswith("| mesh | steps/sub | omega | level | N_t=100 | N_t=200 |")
     assert "| 17 | 20 | 0.01 | one-level | 22 | >420 |" in lines
     assert "| 17 | 20 | 0.01 | two-level | 20 | 21 |" in lines
+
+
+def test_ablation_cases_are_valid_problems_on_the_modal_path():
+    from paper_2305_04421_amd import _lib
+    import ctypes
+    lib = _lib.load()
+    cases = list(ex.ablation_cases())
+    assert {c["variant"] for c in cases} == set(ex.ABLATIONS)
+    for c in cases:
+        params = wl.paper_problem(c["nt"], c["steps_per_sub"], c["omega"], coarse=c["coarse"],
+                                  n_points=c["mesh"])
+        params.update(ex.ABLATIONS[c["variant"]])
+        prob = _lib.make_problem(params, "fp64", "modal")
+        assert lib.kkt_validate(ctypes.byref(prob)) == 0, c
+
+
+def test_ablation_table_lists_variants_in_order():
+    rows = [dict(study="ablation", variant=v, mesh=17, steps_per_sub=5, omega=1e-2, coarse=2, nt=nt,
+                 iters=10 + i, converged=True)
+            for i, v in enumerate(["ASM", "paper"]) for nt in (100, 200)]
+    lines = ex.markdown(rows).splitlines()
+    assert lines[0] == "| steps/sub | omega | variant | N_t=100 | N_t=200 |"
+    assert lines[2].startswith("| 5 | 0.01 | paper | 11 | 11 |")
+    assert lines[3].startswith("| 5 | 0.01 | ASM | 10 | 10 |")
