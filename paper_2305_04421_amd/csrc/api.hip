@@ -186,7 +186,7 @@ int validate(const kktdd_problem* p) {
   auto bad = [](const char* m) { return set_error(KKTDD_EINVAL, m); };
   if (p->nx < 2 || p->ny < 2) return bad("nx and ny must be >= 2");
   if (p->nx > 1024 || p->ny > 1024) return bad("nx and ny must be <= 1024");
-  if (p->nt < 1) return bad("nt must be >= 1");
+  if (p->nt < 1 || p->nt > 65535) return bad("nt must be in 1..65535 (one launch row per time node)");
   const double pos[] = {p->Lx, p->Ly, p->T, p->nu, p->omega};
   for (double v : pos)
     if (!(v > 0.0) || !std::isfinite(v)) return bad("Lx, Ly, T, nu, omega must be positive and finite");

@@ -78,27 +78,50 @@ k_coarse_factor(Geom g, const double* __restrict__ G2, const double* __restrict_
 }
 
 // In-place solve of every mode's band system on padded sine-mode slices xhat[slot][q][p].
-__global__ void __launch_bounds__(kBlock)
+// The substitutions keep the last hb solved values in registers, so the dependency chain
+// runs through registers rather than through memory; the loads of the right-hand side and
+// of the factor do not depend on the chain.
+template <int NB>
+__global__ void __launch_bounds__(64)
 k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat) {
-  const int mode = blockIdx.x * kBlock + threadIdx.x;
+  constexpr int hb = 2 * NB - 1, w = hb + 1;
+  const int mode = blockIdx.x * 64 + threadIdx.x;
   const int nmodes = g.nxy;
   if (mode >= nmodes) return;
   const int q = mode / g.mx, p = mode % g.mx;
   const long long MM = g.padded();
   double* x = xhat + (long long)q * g.Mx + p;
-  const int hb = 2 * g.nb - 1, w = hb + 1;
-  auto L = [&](int i, int j) { return fac[((long long)i * w + (i - j)) * nmodes + mode]; };
-  // forward: L y = r
-  for (int i = 0; i < g.nc; ++i) {
+  const double* Lm = fac + mode;
+  const long long ld = nmodes;
+  const int nc = g.nc;
+  // forward: L y = r;  win[b] = y_{i-1-b}
+  double win[hb];
+#pragma unroll
+  for (int b = 0; b < hb; ++b) win[b] = 0.0;
+  for (int i = 0; i < nc; ++i) {
     double a = x[i * MM];
-    for (int j = (i - hb > 0 ? i - hb : 0); j < i; ++j) a -= L(i, j) * x[j * MM];
-    x[i * MM] = a / L(i, i);
+#pragma unroll
+    for (int b = 1; b <= hb; ++b)
+      if (i - b >= 0) a -= Lm[((long long)i * w + b) * ld] * win[b - 1];
+    const double y = a / Lm[((long long)i * w) * ld];
+    x[i * MM] = y;
+#pragma unroll
+    for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
+    win[0] = y;
   }
-  // backward: L^T c = y
-  for (int i = g.nc - 1; i >= 0; --i) {
+  // backward: L^T c = y;  win[b] = c_{i+1+b}
+#pragma unroll
+  for (int b = 0; b < hb; ++b) win[b] = 0.0;
+  for (int i = nc - 1; i >= 0; --i) {
     double a = x[i * MM];
-    for (int j = i + 1; j <= i + hb && j < g.nc; ++j) a -= L(j, i) * x[j * MM];
-    x[i * MM] = a / L(i, i);
+#pragma unroll
+    for (int b = 1; b <= hb; ++b)
+      if (i + b < nc) a -= Lm[((long long)(i + b) * w + b) * ld] * win[b - 1];
+    const double c = a / Lm[((long long)i * w) * ld];
+    x[i * MM] = c;
+#pragma unroll
+    for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
+    win[0] = c;
   }
 }
 
@@ -116,17 +139,19 @@ __device__ inline double prolong(const Geom& g, const double* __restrict__ slots
   return v;
 }
 
+// One workgroup row per time node: the node's subdomain and linear-basis values are
+// computed once per thread, without 64-bit divisions.
 __global__ void __launch_bounds__(kBlock)
 k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict__ dscale,
                  const double* __restrict__ c0, const double* __restrict__ Dc0,
                  const double* __restrict__ DDc0, double* __restrict__ rp) {
-  const long long e = (long long)blockIdx.x * kBlock + threadIdx.x;
-  if (e >= g.P) return;
+  const int pt = blockIdx.x * kBlock + threadIdx.x;
+  const int n = blockIdx.y + 1;
+  if (pt >= g.nxy) return;
+  const long long e = (long long)(n - 1) * g.nxy + pt;
   const double sc = dscale ? *dscale : 1.0;
   double v = sc * rw[e];
   if (c0) {
-    const int n = (int)(e / g.nxy) + 1;
-    const int pt = (int)(e % g.nxy);
     double Sc = prolong(g, DDc0, n, pt) - prolong(g, Dc0, n + 1, pt);
     if (n >= 2) Sc -= prolong(g, Dc0, n - 1, pt) - prolong(g, c0, n, pt);
     v -= Sc / g.h;
@@ -157,8 +182,12 @@ int launch_coarse_factor(const Geom& g, const double* G2, const double* G0, cons
 
 int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStream_t s) {
   prof_begin(KKTDD_K_COARSE, s);
-  hipLaunchKernelGGL(k_coarse_solve, dim3((g.nxy + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g,
-                     fac, xhat);
+  // 64-thread workgroups spread the (latency-bound) per-mode solves over more CUs
+  const dim3 grid((g.nxy + 63) / 64), block(64);
+  if (g.nb == 2)
+    hipLaunchKernelGGL(k_coarse_solve<2>, grid, block, 0, s, g, fac, xhat);
+  else
+    hipLaunchKernelGGL(k_coarse_solve<1>, grid, block, 0, s, g, fac, xhat);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_COARSE, s, 8.0 * g.nxy * g.nc * (2.0 * g.nb + 2.0), 0.0);
   return 0;
@@ -168,8 +197,8 @@ int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
                           const double* c0, const double* Dc0, const double* DDc0,
                           double* rprime, hipStream_t s) {
   prof_begin(KKTDD_K_COARSE, s);
-  hipLaunchKernelGGL(k_residual_prime, dim3((unsigned)((g.P + kBlock - 1) / kBlock)),
-                     dim3(kBlock), 0, s, g, rw, dscale, c0, Dc0, DDc0, rprime);
+  hipLaunchKernelGGL(k_residual_prime, dim3((g.nxy + kBlock - 1) / kBlock, g.nt), dim3(kBlock), 0,
+                     s, g, rw, dscale, c0, Dc0, DDc0, rprime);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_COARSE, s, 16.0 * g.P, 0.0);
   return 0;

@@ -57,8 +57,11 @@ __device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
 // Work split inside a workgroup: the M/16 column (or row) tiles of a 16-wide block are dealt
 // to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
 // that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
-// ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.
-constexpr int kPD = 4;
+// ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.  The ring is
+// deeper when a wave owns few tiles (few registers per slot, and the chain of one tile is
+// otherwise bound by the L2 round trip).
+template <int TPW>
+constexpr int prefetch_depth() { return TPW == 1 ? 16 : (TPW == 2 ? 8 : 4); }
 
 // ---- plain engines (f64, f32) ----------------------------------------------------------
 template <typename T>
@@ -84,20 +87,24 @@ struct EngPlain {
   template <int TPW>
   static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ S, int M,
                                     int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    constexpr int kPD = prefetch_depth<TPW>();
     const T* A = reinterpret_cast<const T*>(lds);
     const int lda = M + 1;
     const T* Sp = S + (long long)lk * M + wave * 16 + li;
     const long long tstride = (long long)nw * 16;
+    const int nks = M >> 2;
     T bq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
+      if (p < nks) {
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
-    const int nks = M >> 2;
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+      }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
       for (int p = 0; p < kPD; ++p) {
         const int ks = ks0 + p;
+        if (ks >= nks) break;
         const T a = A[li * lda + 4 * ks + lk];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
@@ -113,20 +120,24 @@ struct EngPlain {
   template <int TPW>
   static __device__ void gemm_left(const T* __restrict__ S, const unsigned char* lds, int M,
                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+    constexpr int kPD = prefetch_depth<TPW>();
     const T* B = reinterpret_cast<const T*>(lds);
     // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
     const T* Sp = S + (long long)lk * M + wave * 16 + li;
     const long long tstride = (long long)nw * 16;
+    const int nks = M >> 2;
     T aq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
+      if (p < nks) {
 #pragma unroll
-      for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
-    const int nks = M >> 2;
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+      }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
       for (int p = 0; p < kPD; ++p) {
         const int ks = ks0 + p;
+        if (ks >= nks) break;
         const T b = B[(4 * ks + lk) * 17 + li];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);

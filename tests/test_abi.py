@@ -58,7 +58,7 @@ def test_validate_accepts_the_configurations(lib):
             assert lib.kkt_validate(ctypes.byref(p)) == 0, name
 
 
-@pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(nx=1025), dict(nt=0), dict(omega=0.0),
+@pytest.mark.parametrize("bad", [dict(nx=1), dict(ny=0), dict(nx=1025), dict(nt=0), dict(nt=65536, n_sub=4), dict(omega=0.0),
                                  dict(nu=-1.0), dict(T=float("inf")), dict(Lx=0.0), dict(n_sub=5),
                                  dict(overlap=9), dict(overlap=-1), dict(coarse=3), dict(n_sub=32, coarse=2),
                                  dict(precision=6), dict(sweep=2)])
