@@ -147,6 +147,18 @@ size_t kkt_size(const kktdd_handle* h);
 /* The precision the handle's sweeps run in (KKTDD_AUTO resolved); KKTDD_EINVAL for NULL. */
 int kkt_precision(const kktdd_handle* h);
 
+/* Launch shapes of the sine-transform GEMM kernels (row kernel: kind 0, column kernel: kind 1)
+ * for a padded extent (multiple of 16) and slice count, per precision: waves per workgroup
+ * (dividing extent/16, at most 8 tiles per wave) and a deep L2 prefetch ring (0/1).  kkt_create
+ * measures the candidates on its own extents and keeps the fastest for the process (disable
+ * with KKTDD_AUTOTUNE=0; KKTDD_TUNE_CACHE=<file> keeps them across processes, one JSON object
+ * per line).  Every shape performs the same operations in the same order, so results do not
+ * depend on it.  Host-only; set returns KKTDD_EINVAL for an invalid shape. */
+int kkt_tune_set(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t waves,
+                 int32_t deep);
+int kkt_tune_get(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t* waves,
+                 int32_t* deep);
+
 /* Condition number of the spatial block D_sigma = sigma*I + dt*nu*A_h of the preconditioner's
  * sweeps (Eq. (7) with the shift of Sec. 2), from the extreme sine-mode eigenvalues of A_h.
  * Float32 rounding in the sweeps is amplified by it.  Host-only; -1 for an invalid problem. */

@@ -31,7 +31,7 @@ VARIANTS = {
 MAX_RESTART = 1024
 
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_precision",
-            "kkt_kappa", "kkt_rhs",
+            "kkt_kappa", "kkt_tune_set", "kkt_tune_get", "kkt_rhs",
             "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
             "kkt_profile_read", "kkt_last_error")
 
@@ -86,6 +86,8 @@ def load():
     lib.kkt_precision.restype = ctypes.c_int
     lib.kkt_kappa.argtypes = [P]
     lib.kkt_kappa.restype = dbl
+    lib.kkt_tune_set.argtypes = [i32] * 6
+    lib.kkt_tune_get.argtypes = [i32] * 4 + [ctypes.POINTER(i32)] * 2
     lib.kkt_rhs.argtypes = [vp, vp, vp, vp]
     lib.kkt_apply.argtypes = [vp, vp, vp]
     lib.precond_apply.argtypes = [vp, vp, vp]
@@ -98,7 +100,7 @@ def load():
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
     lib.kkt_last_error.argtypes = []
     lib.kkt_last_error.restype = ctypes.c_char_p
-    for name in ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_rhs", "kkt_apply",
+    for name in ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_tune_set", "kkt_tune_get", "kkt_rhs", "kkt_apply",
                  "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
                  "kkt_profile_read"):
         getattr(lib, name).restype = ctypes.c_int

@@ -574,6 +574,40 @@ int field_sumsq(kktdd_handle* H, const double* r, double out[3]) {
   return 0;
 }
 
+// Launch shapes of the sweep GEMM kernels for this handle's extents (unless KKTDD_AUTOTUNE=0):
+// measured on the handle's zeroed work buffers, once per (extent, slices, engine) per process.
+bool autotune_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("KKTDD_AUTOTUNE");
+    return !(e && std::string(e) == "0");
+  }();
+  return v;
+}
+
+int autotune(kktdd_handle* H) {
+  if (!autotune_enabled()) return 0;
+  const Geom& g = H->g;
+  const int prec = H->prob.precision;
+  const size_t MM = (size_t)g.padded();
+  void *a = nullptr, *b = nullptr;
+  int nslices = 0;
+  if (H->prob.sweep == KKTDD_SWEEP_MODAL) {
+    a = H->Rhat;
+    b = H->Mtmp;
+    nslices = g.nt;
+  } else {
+    a = H->Tbuf;
+    b = H->Ubuf;
+    nslices = g.nd;
+  }
+  const size_t bytes = (size_t)nslices * MM * H->elem;
+  KKT_HIP(hipMemsetAsync(a, 0, bytes, H->stream));
+  KKT_HIP(hipMemsetAsync(b, 0, bytes, H->stream));
+  if (int e = launch_autotune(g, prec, H->Sx(), H->Sy(), H->invlam(), a, b, nslices, H->stream)) return e;
+  KKT_HIP(hipStreamSynchronize(H->stream));
+  return 0;
+}
+
 int ensure_krylov(kktdd_handle* H, int R) {
   if (H->R >= R) return 0;
   const Geom& g = H->g;
@@ -719,6 +753,7 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     return fail(set_error(KKTDD_EHIP, "hipHostMalloc failed"));
   }
   if (int e = build_coarse(H)) return fail(e);
+  if (int e = autotune(H)) return fail(e);
   if (hipStreamSynchronize(H->stream) != hipSuccess) {
     (void)hipGetLastError();
     return fail(set_error(KKTDD_EHIP, "setup failed"));
@@ -740,6 +775,16 @@ void kkt_destroy(kktdd_handle* H) {
 size_t kkt_size(const kktdd_handle* H) { return H ? (size_t)(3 * H->g.P) : 0; }
 
 int kkt_precision(const kktdd_handle* H) { return H ? H->prob.precision : KKTDD_EINVAL; }
+
+int kkt_tune_set(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t waves,
+                 int32_t deep) {
+  return tune_set(kind, precision, extent, nslices, waves, deep);
+}
+
+int kkt_tune_get(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t* waves,
+                 int32_t* deep) {
+  return tune_get(kind, precision, extent, nslices, waves, deep);
+}
 
 double kkt_kappa(const kktdd_problem* prob) {
   if (!prob || validate(prob) != KKTDD_OK) return -1.0;

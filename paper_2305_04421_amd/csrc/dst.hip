@@ -28,7 +28,11 @@
 // bf16 engines) are read straight from L2 using their symmetry, so every operand load is a
 // run of contiguous row segments; the other operand sits in LDS.  Work buffers are float64
 // for the f64 engine and float32 otherwise.
+#include <array>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "internal.h"
 
@@ -58,10 +62,11 @@ __device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
 // to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
 // that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
 // ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.  The ring is
-// deeper when a wave owns few tiles (few registers per slot, and the chain of one tile is
-// otherwise bound by the L2 round trip).
+// PD k-steps deep: 4 by default, deeper (16 for one tile per wave, 8 for two) where the
+// autotuner measured it faster.
+constexpr int kPDDefault = 4;
 template <int TPW>
-constexpr int prefetch_depth() { return TPW == 1 ? 16 : (TPW == 2 ? 8 : 4); }
+constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW == 2 ? 8 : kPDDefault); }
 
 // ---- plain engines (f64, f32) ----------------------------------------------------------
 template <typename T>
@@ -84,10 +89,9 @@ struct EngPlain {
     reinterpret_cast<T*>(lds)[k * 17 + c] = v;
   }
   // acc[t] += A (16 x M) * S(:, tile wave + t*nw), S symmetric M x M.
-  template <int TPW>
+  template <int TPW, int kPD>
   static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ S, int M,
                                     int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
-    constexpr int kPD = prefetch_depth<TPW>();
     const T* A = reinterpret_cast<const T*>(lds);
     const int lda = M + 1;
     const T* Sp = S + (long long)lk * M + wave * 16 + li;
@@ -117,10 +121,9 @@ struct EngPlain {
     }
   }
   // acc[t] += S(row tile wave + t*nw, :) * B (M x 16).
-  template <int TPW>
+  template <int TPW, int kPD>
   static __device__ void gemm_left(const T* __restrict__ S, const unsigned char* lds, int M,
                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
-    constexpr int kPD = prefetch_depth<TPW>();
     const T* B = reinterpret_cast<const T*>(lds);
     // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
     const T* Sp = S + (long long)lk * M + wave * 16 + li;
@@ -200,7 +203,7 @@ struct EngBF {
   static constexpr int ring(int TPW) { return TPW * NP <= 8 ? 2 : 1; }
   // acc[t] += A (16 x M) * S(:, tile wave + t*nw); the B fragment of tile ct is
   // S[32ks + 8lk + i][ct*16 + li] = S[ct*16 + li][32ks + 8lk + i]: 16 contiguous bytes.
-  template <int TPW>
+  template <int TPW, int PD_unused>
   static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ S, int M,
                                     int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
     constexpr int RD = ring(TPW);
@@ -241,7 +244,7 @@ struct EngBF {
     }
   }
   // acc[t] += S(row tile wave + t*nw, :) * B (M x 16, stored transposed in LDS).
-  template <int TPW>
+  template <int TPW, int PD_unused>
   static __device__ void gemm_left(const __bf16* __restrict__ S, const unsigned char* lds, int M,
                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
     constexpr int RD = ring(TPW);
@@ -311,7 +314,7 @@ struct RowArgs {
   long long g2_stride;
 };
 
-template <typename Eng, int TPW>
+template <typename Eng, int TPW, int PD>
 __global__ void __launch_bounds__(512)
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
@@ -361,7 +364,7 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
     const T* src = a.g1_in + s * a.g1_stride + (long long)rb * 16 * Mx;
     for (int e = threadIdx.x; e < 16 * Mx; e += nthr) Eng::put_a(smem_raw, Mx, e / Mx, e % Mx, src[e]);
     __syncthreads();
-    Eng::template gemm_right<TPW>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
+    Eng::template gemm_right<TPW, PD>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
@@ -432,7 +435,7 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   // ---- GEMM2: T = b S_x ------------------------------------------------------------------
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  Eng::template gemm_right<TPW>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
+  Eng::template gemm_right<TPW, PD>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     const int col = (wave + t * nw) * 16 + li;
@@ -458,7 +461,7 @@ struct ColArgs {
   long long out_stride;
 };
 
-template <typename Eng, int TPW>
+template <typename Eng, int TPW, int PD>
 __global__ void __launch_bounds__(512)
 k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
@@ -481,7 +484,7 @@ k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   for (int pass = 0; pass < 1 + a.two; ++pass) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    Eng::template gemm_left<TPW>(Sy, smem_raw, My, wave, nw, li, lk, acc);
+    Eng::template gemm_left<TPW, PD>(Sy, smem_raw, My, wave, nw, li, lk, acc);
     if (pass == 0 && a.invlam) {
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
@@ -527,6 +530,57 @@ inline int waves_for(int M) {
   return 8;   // padded extents make t a multiple of 8 here
 }
 
+// ---- autotuned launch shapes ---------------------------------------------------------------
+// A launch shape is (waves per workgroup, deep prefetch ring).  Every shape runs the same
+// multiply-adds in the same order, so the choice changes the speed only, never the result.
+// Choices are measured per (kernel, engine, extent, slices) and kept for the process (and in
+// the file KKTDD_TUNE_CACHE names, one JSON object per line, when that is set).
+struct Shape {
+  int nw;
+  int deep;
+};
+using TuneKey = std::array<int, 4>;   // kind (0 rows, 1 cols), engine, M, slices
+std::mutex g_tune_mu;
+std::map<TuneKey, Shape> g_tuned;
+bool g_tune_loaded = false;
+
+const char* tune_path() {
+  const char* p = std::getenv("KKTDD_TUNE_CACHE");
+  return (p && *p) ? p : nullptr;
+}
+
+void tune_load_locked() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = tune_path();
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[256];
+  while (std::fgets(line, sizeof line, f)) {
+    int kind, eng, M, ns, nw, deep;
+    if (std::sscanf(line, "{\"kind\": %d, \"engine\": %d, \"M\": %d, \"slices\": %d, \"waves\": %d, "
+                    "\"deep\": %d", &kind, &eng, &M, &ns, &nw, &deep) == 6)
+      g_tuned[{kind, eng, M, ns}] = Shape{nw, deep};
+  }
+  std::fclose(f);
+}
+
+Shape tuned_shape(int kind, int eng, int M, int nslices) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  auto it = g_tuned.find({kind, eng, M, nslices});
+  if (it != g_tuned.end()) return it->second;
+  return Shape{waves_for(M), 0};
+}
+
+template <typename Eng> constexpr int engine_id();
+template <> constexpr int engine_id<EngPlain<double>>() { return KKTDD_FP64; }
+template <> constexpr int engine_id<EngPlain<float>>() { return KKTDD_FP32; }
+template <> constexpr int engine_id<EngBF<1>>() { return KKTDD_BF16; }
+template <> constexpr int engine_id<EngBF<3>>() { return KKTDD_BF16X3; }
+template <> constexpr int engine_id<EngBF<6>>() { return KKTDD_BF16X6; }
+
 // Dynamic LDS above 64 KiB has to be enabled per kernel before the first launch.
 template <typename F>
 int allow_lds(F* kernel, size_t lds) {
@@ -537,54 +591,67 @@ int allow_lds(F* kernel, size_t lds) {
 }
 
 // Algorithmic flops of one launch: 2*my*mx*mx per right product, 2*my*my*mx per left product.
-template <typename Eng, int TPW>
+template <typename Eng, int TPW, int PD>
 int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
   const size_t lds = Eng::rows_lds(g.Mx);
-  if (int e = allow_lds(k_rows<Eng, TPW>, lds)) return e;
+  if (int e = allow_lds(k_rows<Eng, TPW, PD>, lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_rows<Eng, TPW>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, 2.0 * ngemm * nslices * (double)g.my * g.mx * g.mx);
   return 0;
 }
 
-template <typename Eng, int TPW>
+template <typename Eng, int TPW, int PD>
 int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
   const size_t lds = Eng::cols_lds(g.My);
-  if (int e = allow_lds(k_cols<Eng, TPW>, lds)) return e;
+  if (int e = allow_lds(k_cols<Eng, TPW, PD>, lds)) return e;
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_cols<Eng, TPW>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  hipLaunchKernelGGL((k_cols<Eng, TPW, PD>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, 2.0 * (1 + a.two) * nslices * (double)g.my * g.my * g.mx);
   return 0;
 }
 
-#define KKT_TPW_DISPATCH(FN, TPWV, ...)                  \
-  switch (TPWV) {                                        \
-    case 1: return FN<Eng, 1>(__VA_ARGS__);              \
-    case 2: return FN<Eng, 2>(__VA_ARGS__);              \
-    case 3: return FN<Eng, 3>(__VA_ARGS__);              \
-    case 4: return FN<Eng, 4>(__VA_ARGS__);              \
-    case 5: return FN<Eng, 5>(__VA_ARGS__);              \
-    case 6: return FN<Eng, 6>(__VA_ARGS__);              \
-    case 7: return FN<Eng, 7>(__VA_ARGS__);              \
-    case 8: return FN<Eng, 8>(__VA_ARGS__);              \
-    default: return set_error(KKTDD_EINVAL, "unsupported tile count"); \
+// (tiles per wave, deep ring) -> instantiation; deep rings exist for one and two tiles only.
+#define KKT_TPW_DISPATCH(FN, TPWV, DEEP, ...)                                            \
+  switch (TPWV) {                                                                        \
+    case 1: return (DEEP) ? FN<Eng, 1, deep_prefetch<1>()>(__VA_ARGS__)                  \
+                          : FN<Eng, 1, kPDDefault>(__VA_ARGS__);                         \
+    case 2: return (DEEP) ? FN<Eng, 2, deep_prefetch<2>()>(__VA_ARGS__)                  \
+                          : FN<Eng, 2, kPDDefault>(__VA_ARGS__);                         \
+    case 3: return FN<Eng, 3, kPDDefault>(__VA_ARGS__);                                  \
+    case 4: return FN<Eng, 4, kPDDefault>(__VA_ARGS__);                                  \
+    case 5: return FN<Eng, 5, kPDDefault>(__VA_ARGS__);                                  \
+    case 6: return FN<Eng, 6, kPDDefault>(__VA_ARGS__);                                  \
+    case 7: return FN<Eng, 7, kPDDefault>(__VA_ARGS__);                                  \
+    case 8: return FN<Eng, 8, kPDDefault>(__VA_ARGS__);                                  \
+    default: return set_error(KKTDD_EINVAL, "unsupported tile count");                   \
   }
 
 template <typename Eng>
+int rows_shape(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, Shape sh,
+               int kclass, hipStream_t s) {
+  KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / sh.nw, sh.deep, g, a, nslices, sh.nw, kclass, s)
+}
+
+template <typename Eng>
+int cols_shape(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, Shape sh,
+               int kclass, hipStream_t s) {
+  KKT_TPW_DISPATCH(cols_t, g.My / 16 / sh.nw, sh.deep, g, a, nslices, sh.nw, kclass, s)
+}
+
+template <typename Eng>
 int rows(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
-  const int nw = waves_for(g.Mx);
-  KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / nw, g, a, nslices, nw, kclass, s)
+  return rows_shape<Eng>(g, a, nslices, tuned_shape(0, engine_id<Eng>(), g.Mx, nslices), kclass, s);
 }
 
 template <typename Eng>
 int cols(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
-  const int nw = waves_for(g.My);
-  KKT_TPW_DISPATCH(cols_t, g.My / 16 / nw, g, a, nslices, nw, kclass, s)
+  return cols_shape<Eng>(g, a, nslices, tuned_shape(1, engine_id<Eng>(), g.My, nslices), kclass, s);
 }
 
 template <typename T>
@@ -726,6 +793,89 @@ int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in,
   return rows<Eng>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s);
 }
 
+// Measure every launch shape of the row and column kernels on one sweep step's worth of
+// slices (both products of each kernel, on the handle's work buffers) and keep the fastest.
+template <typename Eng>
+int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam, void* bufA,
+               void* bufB, int nslices, hipStream_t s) {
+  using T = typename Eng::data_t;
+  const long long MM = g.padded();
+  RowArgs<T> r = row_args<T>(Sx);
+  r.g1_in = static_cast<const T*>(bufA);
+  r.g1_stride = MM;
+  r.b_mode = B_H_Y;
+  r.g2_out = static_cast<T*>(bufB);
+  r.g2_stride = MM;
+  ColArgs<T> c{Sy, static_cast<const T*>(bufA), MM, static_cast<const T*>(invlam), 1,
+               static_cast<T*>(bufB), MM};
+  hipEvent_t e0, e1;
+  KKT_HIP(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return set_error(KKTDD_EHIP, "hipEventCreate failed");
+  }
+  int rc = 0;
+  for (int kind = 0; kind < 2 && rc == 0; ++kind) {
+    const int M = kind == 0 ? g.Mx : g.My;
+    const TuneKey key{kind, engine_id<Eng>(), M, nslices};
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      tune_load_locked();
+      if (g_tuned.count(key)) continue;
+    }
+    const int t = M / 16;
+    Shape best{waves_for(M), 0};
+    float best_us = 1e30f;
+    int cand[4], nc = 0;
+    for (int nw : {2, 4, 8, t}) {
+      if (nw < 1 || nw > 8 || t % nw != 0 || t / nw > 8) continue;
+      bool seen = false;
+      for (int i = 0; i < nc; ++i) seen = seen || cand[i] == nw;
+      if (!seen) cand[nc++] = nw;
+    }
+    for (int ci = 0; ci < nc; ++ci) {
+      const int nw = cand[ci];
+      for (int deep = 0; deep <= (t / nw <= 2 ? 1 : 0); ++deep) {
+        const Shape sh{nw, deep};
+        auto launch = [&]() {
+          return kind == 0 ? rows_shape<Eng>(g, r, nslices, sh, KKTDD_K_OTHER, s)
+                           : cols_shape<Eng>(g, c, nslices, sh, KKTDD_K_OTHER, s);
+        };
+        if ((rc = launch())) break;
+        if (hipEventRecord(e0, s) != hipSuccess) { rc = set_error(KKTDD_EHIP, "hipEventRecord failed"); break; }
+        for (int rep = 0; rep < 3 && rc == 0; ++rep) rc = launch();
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = set_error(KKTDD_EHIP, "autotune timing failed");
+          break;
+        }
+        const float us = 1e3f * ms / 3.f;
+        if (us < best_us) {
+          best_us = us;
+          best = sh;
+        }
+      }
+      if (rc) break;
+    }
+    if (rc) break;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[key] = best;
+    if (const char* path = tune_path()) {
+      if (FILE* f = std::fopen(path, "a")) {
+        std::fprintf(f, "{\"kind\": %d, \"engine\": %d, \"M\": %d, \"slices\": %d, \"waves\": %d, "
+                        "\"deep\": %d, \"us\": %.2f}\n", kind, engine_id<Eng>(), M, nslices, best.nw,
+                     best.deep, best_us);
+        std::fclose(f);
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return rc;
+}
+
 }  // namespace
 
 #define KKT_ENGINE_DISPATCH(PREC, FN, ...)                                    \
@@ -788,6 +938,37 @@ int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const 
   r.out_mode = OUT_PLAIN;
   r.out64 = c0;
   return rows<EngPlain<double>>(g, r, g.nc, KKTDD_K_COARSE, s);
+}
+
+}  // namespace kktdd
+
+namespace kktdd {
+
+int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep) {
+  const int t = extent / 16;
+  if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 16 ||
+      extent % 16 != 0 || nslices < 1 || waves < 1 || waves > 8 || t % waves != 0 ||
+      t / waves > 8 || deep < 0 || deep > 1)
+    return set_error(KKTDD_EINVAL, "invalid launch shape");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_load_locked();
+  g_tuned[{kind, precision, extent, nslices}] = Shape{waves, deep};
+  return 0;
+}
+
+int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep) {
+  if (!waves || !deep || extent < 16 || extent % 16 != 0)
+    return set_error(KKTDD_EINVAL, "invalid launch-shape query");
+  const Shape sh = tuned_shape(kind, precision, extent, nslices);
+  *waves = sh.nw;
+  *deep = sh.deep;
+  return 0;
+}
+
+int launch_autotune(const Geom& g, int precision, const void* Sx, const void* Sy,
+                    const void* invlam, void* bufA, void* bufB, int nslices, hipStream_t s) {
+  if (nslices <= 0) return 0;
+  KKT_ENGINE_DISPATCH(precision, autotune_t, g, Sx, Sy, invlam, bufA, bufB, nslices, s)
 }
 
 }  // namespace kktdd

@@ -109,6 +109,14 @@ int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void*
                        const double* c0, hipStream_t s);
 
 // ---- modal.hip: transform-hoisted Schur block (sine-mode space) --------------------------
+// Autotuner: measure the launch shapes of the row and column kernels for this extent and
+// slice count on two work buffers (each nslices padded slices) and keep the fastest.
+int launch_autotune(const Geom& g, int precision, const void* Sx, const void* Sy,
+                    const void* invlam, void* bufA, void* bufB, int nslices, hipStream_t s);
+
+int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep);
+int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep);
+
 int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
                           hipStream_t s);
 int launch_modal_sweeps(const Geom& g, int precision, const void* rhat, const double* c0,

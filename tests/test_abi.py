@@ -136,6 +136,20 @@ def test_variant_memory_plan():
     assert memory_plan(dict(base, local="exact"), "auto", 0, sweep="modal") == exact
 
 
+def test_launch_shape_table(lib):
+    from paper_2305_04421_amd import _lib
+    w, d = ctypes.c_int32(), ctypes.c_int32()
+    # no entry: the default shape (8 waves for 32 tiles, shallow ring)
+    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d)) == 0
+    assert (w.value, d.value) == (8, 0)
+    assert lib.kkt_tune_set(1, _lib.FP32, 512, 7, 4, 1) == 0
+    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d)) == 0
+    assert (w.value, d.value) == (4, 1)
+    for bad in [(2, 0, 128, 4, 8, 0), (0, 9, 128, 4, 8, 0), (0, 0, 100, 4, 4, 0), (0, 0, 128, 4, 3, 0),
+                (0, 0, 512, 4, 2, 0), (0, 0, 128, 0, 8, 0), (0, 0, 128, 4, 8, 2)]:
+        assert lib.kkt_tune_set(*bad) == _lib.EINVAL, bad
+
+
 def test_memory_plan_of_a_long_cycle(lib):
     # the unrestarted solves of the weak-scaling experiment keep up to 421 basis vectors
     p = _prob(nx=16, ny=16, nt=256, n_sub=16)

@@ -132,6 +132,37 @@ def test_precond_degenerate_one_level(sweep):
     assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-12
 
 
+@pytest.mark.parametrize("precision,sweep", [("fp64", "step"), ("fp32", "step"), ("bf16x3", "step"),
+                                             ("fp64", "modal")])
+def test_launch_shapes_give_identical_results(precision, sweep):
+    """Every launch shape of the transform kernels (waves per workgroup, prefetch depth)
+    performs the same operations in the same order: the preconditioner is bitwise equal."""
+    import ctypes
+    from paper_2305_04421_amd import _lib
+    lib = _lib.load()
+    params = CASES["full_tiles_overlap_k"]    # padded extents 128 (x) and 64 (y), 4 subdomains
+    p = Problem(**params).validate()
+    r = dev(wl.random_field((3,) + p.field_shape, 21))
+    prec = _lib.PRECISIONS[precision]
+    with solver(params, precision, sweep=sweep) as S:
+        ns = p.nt if sweep == "modal" else p.n_sub
+        saved = []
+        for kind, M in ((0, 128), (1, 64)):
+            w, d = ctypes.c_int32(), ctypes.c_int32()
+            assert lib.kkt_tune_get(kind, prec, M, ns, ctypes.byref(w), ctypes.byref(d)) == 0
+            saved.append((kind, M, w.value, d.value))
+        ref = S.precond(r).clone()
+        try:
+            for rows_shape, cols_shape in [((8, 0), (4, 1)), ((8, 1), (2, 0)), ((4, 1), (1, 0)),
+                                           ((2, 0), (4, 0)), ((4, 0), (2, 1))]:
+                assert lib.kkt_tune_set(0, prec, 128, ns, *rows_shape) == 0
+                assert lib.kkt_tune_set(1, prec, 64, ns, *cols_shape) == 0
+                assert torch.equal(S.precond(r), ref), (rows_shape, cols_shape)
+        finally:
+            for kind, M, w, d in saved:
+                lib.kkt_tune_set(kind, prec, M, ns, w, d)
+
+
 def test_precond_is_deterministic():
     params = CASES["tiny32"]
     p = Problem(**params).validate()
