@@ -102,7 +102,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); this build has no "
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solver has no "
               "multi-GPU path.", file=sys.stderr)
         return 2
     import numpy as np
