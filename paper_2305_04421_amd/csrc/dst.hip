@@ -62,11 +62,11 @@ __device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
 // to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
 // that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
 // ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.  The ring is
-// PD k-steps deep: 4 by default, deeper (16 for one tile per wave, 8 for two) where the
-// autotuner measured it faster.
+// PD k-steps deep: 4 by default, deeper (16 for one tile per wave, 8 for two to four) where
+// the autotuner measured it faster.
 constexpr int kPDDefault = 4;
 template <int TPW>
-constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW == 2 ? 8 : kPDDefault); }
+constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
 
 // ---- plain engines (f64, f32) ----------------------------------------------------------
 template <typename T>
@@ -616,15 +616,17 @@ int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, i
   return 0;
 }
 
-// (tiles per wave, deep ring) -> instantiation; deep rings exist for one and two tiles only.
+// (tiles per wave, deep ring) -> instantiation; deep rings exist for up to four tiles.
 #define KKT_TPW_DISPATCH(FN, TPWV, DEEP, ...)                                            \
   switch (TPWV) {                                                                        \
     case 1: return (DEEP) ? FN<Eng, 1, deep_prefetch<1>()>(__VA_ARGS__)                  \
                           : FN<Eng, 1, kPDDefault>(__VA_ARGS__);                         \
     case 2: return (DEEP) ? FN<Eng, 2, deep_prefetch<2>()>(__VA_ARGS__)                  \
                           : FN<Eng, 2, kPDDefault>(__VA_ARGS__);                         \
-    case 3: return FN<Eng, 3, kPDDefault>(__VA_ARGS__);                                  \
-    case 4: return FN<Eng, 4, kPDDefault>(__VA_ARGS__);                                  \
+    case 3: return (DEEP) ? FN<Eng, 3, deep_prefetch<3>()>(__VA_ARGS__)                  \
+                          : FN<Eng, 3, kPDDefault>(__VA_ARGS__);                         \
+    case 4: return (DEEP) ? FN<Eng, 4, deep_prefetch<4>()>(__VA_ARGS__)                  \
+                          : FN<Eng, 4, kPDDefault>(__VA_ARGS__);                         \
     case 5: return FN<Eng, 5, kPDDefault>(__VA_ARGS__);                                  \
     case 6: return FN<Eng, 6, kPDDefault>(__VA_ARGS__);                                  \
     case 7: return FN<Eng, 7, kPDDefault>(__VA_ARGS__);                                  \
@@ -835,7 +837,7 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     }
     for (int ci = 0; ci < nc; ++ci) {
       const int nw = cand[ci];
-      for (int deep = 0; deep <= (t / nw <= 2 ? 1 : 0); ++deep) {
+      for (int deep = 0; deep <= (t / nw <= 4 ? 1 : 0); ++deep) {
         const Shape sh{nw, deep};
         auto launch = [&]() {
           return kind == 0 ? rows_shape<Eng>(g, r, nslices, sh, KKTDD_K_OTHER, s)
