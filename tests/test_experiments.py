@@ -62,3 +62,13 @@ def test_ablation_table_lists_variants_in_order():
     assert lines[0] == "| steps/sub | omega | variant | N_t=100 | N_t=200 |"
     assert lines[2].startswith("| 5 | 0.01 | paper | 11 | 11 |")
     assert lines[3].startswith("| 5 | 0.01 | ASM | 10 | 10 |")
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
