@@ -94,34 +94,64 @@ k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat
   const double* Lm = fac + mode;
   const long long ld = nmodes;
   const int nc = g.nc;
+  // Row i of the band factor: L(i,i) and L(i,i-b), b = 1..hb, at Lm[(i*w + b)*ld].  The loads of
+  // row i+1 (and of the next right-hand side) are issued before row i is used, so their
+  // latency overlaps the substitution chain.
+  auto load_row = [&](int i, double (&row)[w]) {
+#pragma unroll
+    for (int b = 0; b < w; ++b) row[b] = (i >= 0 && i < nc) ? Lm[((long long)i * w + b) * ld] : 0.0;
+  };
   // forward: L y = r;  win[b] = y_{i-1-b}
   double win[hb];
 #pragma unroll
   for (int b = 0; b < hb; ++b) win[b] = 0.0;
+  double cur[w], nxt[w];
+  load_row(0, cur);
+  double rcur = x[0], rnxt = 0.0;
   for (int i = 0; i < nc; ++i) {
-    double a = x[i * MM];
+    load_row(i + 1, nxt);
+    if (i + 1 < nc) rnxt = x[(i + 1) * MM];
+    double a = rcur;
 #pragma unroll
     for (int b = 1; b <= hb; ++b)
-      if (i - b >= 0) a -= Lm[((long long)i * w + b) * ld] * win[b - 1];
-    const double y = a / Lm[((long long)i * w) * ld];
+      if (i - b >= 0) a -= cur[b] * win[b - 1];
+    const double y = a / cur[0];
     x[i * MM] = y;
 #pragma unroll
     for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
     win[0] = y;
+#pragma unroll
+    for (int b = 0; b < w; ++b) cur[b] = nxt[b];
+    rcur = rnxt;
   }
-  // backward: L^T c = y;  win[b] = c_{i+1+b}
+  // backward: L^T c = y;  win[b] = c_{i+1+b}.  Needs L(i+b, i) = row i+b, entry b, and
+  // L(i,i); the column of the factor below the diagonal is kept in a rolling window.
 #pragma unroll
   for (int b = 0; b < hb; ++b) win[b] = 0.0;
+  double below[hb + 1][w];   // rows i, i+1, .., i+hb of the factor
+#pragma unroll
+  for (int d = 0; d <= hb; ++d) load_row(nc - 1 + d, below[d]);
+  double ycur = x[(nc - 1) * MM], ynxt = 0.0;
   for (int i = nc - 1; i >= 0; --i) {
-    double a = x[i * MM];
+    double prev[w];
+    load_row(i - 1, prev);
+    if (i - 1 >= 0) ynxt = x[(i - 1) * MM];
+    double a = ycur;
 #pragma unroll
     for (int b = 1; b <= hb; ++b)
-      if (i + b < nc) a -= Lm[((long long)(i + b) * w + b) * ld] * win[b - 1];
-    const double c = a / Lm[((long long)i * w) * ld];
+      if (i + b < nc) a -= below[b][b] * win[b - 1];
+    const double c = a / below[0][0];
     x[i * MM] = c;
 #pragma unroll
     for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
     win[0] = c;
+#pragma unroll
+    for (int d = hb; d > 0; --d)
+#pragma unroll
+      for (int b = 0; b < w; ++b) below[d][b] = below[d - 1][b];
+#pragma unroll
+    for (int b = 0; b < w; ++b) below[0][b] = prev[b];
+    ycur = ynxt;
   }
 }
 
@@ -129,34 +159,51 @@ k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat
 // With g^n = (J_hat^T c)^n = D c^n - c^{n+1} and (J_hat g)^n = D g^n - g^{n-1}:
 //     (S_hat c)^n = (1/h) (D^2 c^n - D c^{n+1} - [n>=2] (D c^{n-1} - c^n)),
 // where D c and D^2 c are prolonged from the precomputed D c0 and D^2 c0 (Z commutes with D).
-__device__ inline double prolong(const Geom& g, const double* __restrict__ slots, int node,
-                                 int pt) {
-  if (node < 1 || node > g.nt) return 0.0;
-  const int s = (node - 1) / g.k;
-  const double* c = slots + (long long)(g.nb * s) * g.nxy + pt;
-  double v = c[0];
-  if (g.nb == 2) v += phi1(node, s, g.k) * c[g.nxy];
-  return v;
-}
-
-// One workgroup row per time node: the node's subdomain and linear-basis values are
-// computed once per thread, without 64-bit divisions.
+// One thread per interior point and subdomain marches over the subdomain's owned nodes.  The
+// coarse slots of the subdomain (and the D c0 slots of its neighbours, needed at its first and
+// last node) are loaded once, so the per-node work is one load of r_w and one store.
 __global__ void __launch_bounds__(kBlock)
 k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict__ dscale,
                  const double* __restrict__ c0, const double* __restrict__ Dc0,
                  const double* __restrict__ DDc0, double* __restrict__ rp) {
   const int pt = blockIdx.x * kBlock + threadIdx.x;
-  const int n = blockIdx.y + 1;
+  const int s = blockIdx.y;
   if (pt >= g.nxy) return;
-  const long long e = (long long)(n - 1) * g.nxy + pt;
   const double sc = dscale ? *dscale : 1.0;
-  double v = sc * rw[e];
-  if (c0) {
-    double Sc = prolong(g, DDc0, n, pt) - prolong(g, Dc0, n + 1, pt);
-    if (n >= 2) Sc -= prolong(g, Dc0, n - 1, pt) - prolong(g, c0, n, pt);
-    v -= Sc / g.h;
+  const long long nxy = g.nxy;
+  const int n0 = s * g.k + 1, n1 = (s + 1) * g.k;
+  if (!c0) {
+    for (int n = n0; n <= n1; ++n) {
+      const long long e = (long long)(n - 1) * nxy + pt;
+      rp[e] = sc * rw[e];
+    }
+    return;
   }
-  rp[e] = v;
+  const bool lin = g.nb == 2;
+  auto slot = [&](const double* X, int sd, int b) { return X[(long long)(g.nb * sd + b) * nxy + pt]; };
+  const double C0 = slot(c0, s, 0), C1 = lin ? slot(c0, s, 1) : 0.0;
+  const double D0 = slot(Dc0, s, 0), D1 = lin ? slot(Dc0, s, 1) : 0.0;
+  const double E0 = slot(DDc0, s, 0), E1 = lin ? slot(DDc0, s, 1) : 0.0;
+  const bool hasP = s > 0, hasN = s + 1 < g.nd;
+  const double P0 = hasP ? slot(Dc0, s - 1, 0) : 0.0, P1 = (hasP && lin) ? slot(Dc0, s - 1, 1) : 0.0;
+  const double N0 = hasN ? slot(Dc0, s + 1, 0) : 0.0, N1 = (hasN && lin) ? slot(Dc0, s + 1, 1) : 0.0;
+  const double invh = 1.0 / g.h;
+  for (int n = n0; n <= n1; ++n) {
+    const double ph = lin ? phi1(n, s, g.k) : 0.0;
+    // (S_hat c)^n = (1/h) (D^2 c^n - D c^{n+1} - [n>=2] (D c^{n-1} - c^n)), prolonged from slots
+    double Dnext = 0.0;
+    if (n < n1) Dnext = D0 + (lin ? phi1(n + 1, s, g.k) : 0.0) * D1;
+    else if (hasN) Dnext = N0 + (lin ? phi1(n + 1, s + 1, g.k) : 0.0) * N1;
+    double Sc = (E0 + ph * E1) - Dnext;
+    if (n >= 2) {
+      double Dprev = 0.0;
+      if (n > n0) Dprev = D0 + (lin ? phi1(n - 1, s, g.k) : 0.0) * D1;
+      else if (hasP) Dprev = P0 + (lin ? phi1(n - 1, s - 1, g.k) : 0.0) * P1;
+      Sc -= Dprev - (C0 + ph * C1);
+    }
+    const long long e = (long long)(n - 1) * nxy + pt;
+    rp[e] = sc * rw[e] - Sc * invh;
+  }
 }
 
 }  // namespace
@@ -197,7 +244,7 @@ int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
                           const double* c0, const double* Dc0, const double* DDc0,
                           double* rprime, hipStream_t s) {
   prof_begin(KKTDD_K_COARSE, s);
-  hipLaunchKernelGGL(k_residual_prime, dim3((g.nxy + kBlock - 1) / kBlock, g.nt), dim3(kBlock), 0,
+  hipLaunchKernelGGL(k_residual_prime, dim3((g.nxy + kBlock - 1) / kBlock, g.nd), dim3(kBlock), 0,
                      s, g, rw, dscale, c0, Dc0, DDc0, rprime);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_COARSE, s, 16.0 * g.P, 0.0);
