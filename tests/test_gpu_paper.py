@@ -101,3 +101,34 @@ def test_two_level_is_flat_and_one_level_grows():
     assert max(two) - min(two) <= 4, two
     assert all(b > a for a, b in zip(one, one[1:])), one
     assert one[-1] >= 4 * two[-1], (one, two)
+
+
+def test_mesh_size_is_not_a_factor():
+    """Sec. 4: the two-level count barely changes between 9x9, 17x17 and 33x33 mesh points."""
+    from paper_2305_04421_amd import KKTSolver
+    counts = []
+    for n_points in (9, 17, 33):
+        params = wl.paper_problem(200, 20, 1e-2, coarse=2, n_points=n_points)
+        f = paper_rhs(params)
+        with KKTSolver(params, sweep="modal") as S:
+            _, st = S.solve(dev(f), restart=420, maxit=420, rtol=1e-6)
+        assert st["status"] == 0
+        counts.append(st["iters"])
+    assert max(counts) - min(counts) <= 2, counts
+
+
+def test_two_level_is_robust_in_omega():
+    """Sec. 4 (Fig. 2): over five orders of magnitude of omega the two-level count stays within
+    a narrow band while the one-level count varies strongly."""
+    from paper_2305_04421_amd import KKTSolver
+    two, one = [], []
+    for omega in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5):
+        for coarse, out in ((2, two), (0, one)):
+            params = wl.paper_problem(400, 5, omega, coarse=coarse, n_points=9)
+            f = paper_rhs(params)
+            with KKTSolver(params, sweep="modal") as S:
+                _, st = S.solve(dev(f), restart=420, maxit=420, rtol=1e-6)
+            assert st["status"] == 0
+            out.append(st["iters"])
+    assert max(two) - min(two) <= 6, two
+    assert max(one) >= 3 * max(two), (one, two)
