@@ -334,49 +334,60 @@ k_dcgs_update(long long n, double* V, long long ldv, int j, const double* __rest
   block_sums<1>(out, 1, partials + blockIdx.x);
 }
 
-// One-thread bookkeeping of a DCGS2 step.  vinv[i] scales slot i (1 for final vectors).
+// Bookkeeping of a DCGS2 step by one wave (lane l handles entries l, l+64, ...; the two
+// inner sums are reduced in a fixed order).  vinv[i] scales slot i (1 for final vectors).
 // rec (host-visible) = [alpha, nu, a_0..a_{j-1}, b_0..b_{j-1}, hjj, nu_next, breakdown]
 //   stage 1 (sums of a full step):   reorthogonalisation of the candidate, projection of W,
 //                                    update coefficients; gate = 0 on breakdown
 //   stage 2 (sum of ||W'||^2):       normalisation scales of slots j and j+1
 //   stage 3 (sums without W):        reorthogonalisation coefficients only (closing a column)
-__global__ void k_dcgs_finish(int j, const double* __restrict__ sums, double* __restrict__ vinv,
-                              double* __restrict__ coef, double* __restrict__ rec,
-                              int* __restrict__ gate, int stage) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ void __launch_bounds__(64)
+k_dcgs_finish(int j, const double* __restrict__ sums, double* __restrict__ vinv,
+              double* __restrict__ coef, double* __restrict__ rec, int* __restrict__ gate,
+              int stage) {
+  if (blockIdx.x != 0) return;
+  const int l = threadIdx.x;
   double* a = rec + 2;
   double* b = rec + 2 + j;
   if (stage == 1 || stage == 3) {
     const double sc = vinv[j];
     double sa = 0.0;
-    for (int i = 0; i < j; ++i) {
-      a[i] = vinv[i] * sc * sums[i];
-      sa += a[i] * a[i];
+    for (int i = l; i < j; i += 64) {
+      const double ai = vinv[i] * sc * sums[i];
+      a[i] = ai;
+      sa += ai * ai;
     }
+    sa = wave_sum(sa);
     const double c = sc * sc * sums[2 * j];
     const double al2 = c - sa;
     const bool brk = !(al2 > 1e-24 * c) || !(c > 0.0);
     const double alpha = brk ? 0.0 : sqrt(al2);
-    rec[0] = alpha;
-    rec[1] = sc > 0.0 ? 1.0 / sc : 0.0;
-    rec[2 * j + 4] = brk ? 1.0 : 0.0;
+    if (l == 0) {
+      rec[0] = alpha;
+      rec[1] = sc > 0.0 ? 1.0 / sc : 0.0;
+      rec[2 * j + 4] = brk ? 1.0 : 0.0;
+    }
     if (stage == 3) return;
     double ab = 0.0;
-    for (int i = 0; i < j; ++i) {
-      b[i] = vinv[i] * sums[j + i];
-      ab += a[i] * b[i];
+    for (int i = l; i < j; i += 64) {
+      const double bi = vinv[i] * sums[j + i];
+      b[i] = bi;
+      ab += a[i] * bi;
     }
+    ab = wave_sum(ab);
     const double e = sc * sums[2 * j + 1];
     const double hjj = brk ? 0.0 : (e - ab) / alpha;
-    rec[2 * j + 2] = hjj;
-    coef[0] = brk ? 0.0 : sc / alpha;
-    coef[1] = hjj;
-    for (int i = 0; i < j; ++i) {
+    for (int i = l; i < j; i += 64) {
       coef[2 + i] = brk ? 0.0 : a[i] * vinv[i] / alpha;
       coef[2 + j + i] = b[i] * vinv[i];
     }
-    *gate = brk ? 0 : 1;
-  } else if (*gate) {
+    if (l == 0) {
+      rec[2 * j + 2] = hjj;
+      coef[0] = brk ? 0.0 : sc / alpha;
+      coef[1] = hjj;
+      *gate = brk ? 0 : 1;
+    }
+  } else if (l == 0 && *gate) {
     const double nu = sqrt(sums[0]);
     rec[2 * j + 3] = nu;
     vinv[j] = 1.0;
