@@ -72,7 +72,7 @@ DESCRIPTIONS = {
 # kernel class, as recorded in profiles/arnoldi_<workload>_fp64_hbm_counters.md for the
 # current kernels.  A class whose kernels changed since the counters were taken, or a
 # workload without counters, is absent (traffic null).
-TRAFFIC = {"grid128": {"matvec": 215.84e6}}
+TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.81e6}}
 
 
 def parse():
