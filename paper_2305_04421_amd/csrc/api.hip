@@ -372,11 +372,29 @@ double sinpi_frac(long long r, long long n) {
 int build_tables(kktdd_handle* H) {
   const Geom& g = H->g;
   const kktdd_problem& p = H->prob;
-  auto sine = [](int n, int M) {
-    std::vector<double> S((size_t)M * M, 0.0);
-    for (int a = 0; a < n - 1; ++a)
-      for (int b = 0; b < n - 1; ++b) S[(size_t)a * M + b] = sinpi_frac((long long)(a + 1) * (b + 1), n);
-    return S;
+  // Half-size transform blocks of one extent (n intervals, padded extent M = 2H), block b at
+  // b*H*H: F_b[k][j] = sin(pi f_b(j) (k+1) / n), f_0(j) = 2j+1 for k, j < ceil(m/2) and
+  // f_1(j) = 2j+2 for k, j < floor(m/2), zero elsewhere; `transposed` stores F_b^T.
+  auto half = [](int n, int M, bool transposed) {
+    const int H = M / 2, m = n - 1, A = (m + 1) / 2, B = m / 2;
+    std::vector<double> Q((size_t)M * H, 0.0);
+    for (int b = 0; b < 2; ++b) {
+      const int lim = b == 0 ? A : B;
+      for (int k = 0; k < lim; ++k)
+        for (int j = 0; j < lim; ++j)
+          Q[(size_t)b * H * H + (transposed ? (size_t)j * H + k : (size_t)k * H + j)] =
+              sinpi_frac((long long)(2 * j + 1 + b) * (k + 1), n);
+    }
+    return Q;
+  };
+  // Engine operand of one extent: forward blocks, then inverse blocks.  The plain engines
+  // reduce over the row index of what they read (forward F, inverse F^T); the bfloat16 engines
+  // over the column index (forward F^T, inverse F).
+  auto sine = [&](int n, int M, bool bf) {
+    std::vector<double> f = half(n, M, bf);
+    const std::vector<double> i = half(n, M, !bf);
+    f.insert(f.end(), i.begin(), i.end());
+    return f;
   };
   const double dx = p.Lx / p.nx, dy = p.Ly / p.ny, dtnu = g.dt * p.nu;
   std::vector<double> lx(g.mx), ly(g.my);
@@ -388,11 +406,12 @@ int build_tables(kktdd_handle* H) {
     const double s = std::sin(M_PI * (a + 1) / (2.0 * p.ny));
     ly[a] = dtnu * 4.0 / (dy * dy) * s * s;
   }
-  const std::vector<double> Sx = sine(p.nx, g.Mx), Sy = sine(p.ny, g.My);
+  const std::vector<double> Sx = sine(p.nx, g.Mx, false), Sy = sine(p.ny, g.My, false);
   const double norm = 4.0 / ((double)p.nx * p.ny);
-  std::vector<double> inv((size_t)g.padded(), 0.0);
+  std::vector<double> inv((size_t)g.padded(), 0.0);   // mode order of mode_pos
   for (int q = 0; q < g.my; ++q)
-    for (int a = 0; a < g.mx; ++a) inv[(size_t)q * g.Mx + a] = norm / (g.sigma + ly[q] + lx[a]);
+    for (int a = 0; a < g.mx; ++a)
+      inv[(size_t)mode_pos(q, g.My) * g.Mx + mode_pos(a, g.Mx)] = norm / (g.sigma + ly[q] + lx[a]);
   auto to32 = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
   if (is_bf16(p.precision)) {
     auto parts = [](const std::vector<double>& S) {
@@ -408,7 +427,15 @@ int build_tables(kktdd_handle* H) {
       }
       return out;
     };
-    const std::vector<uint16_t> bx = parts(Sx), by = parts(Sy);
+    // three parts of the forward blocks, then three of the inverse blocks
+    auto parts2 = [&](const std::vector<double>& S) {
+      const size_t h = S.size() / 2;
+      std::vector<uint16_t> a = parts(std::vector<double>(S.begin(), S.begin() + h));
+      const std::vector<uint16_t> b = parts(std::vector<double>(S.begin() + h, S.end()));
+      a.insert(a.end(), b.begin(), b.end());
+      return a;
+    };
+    const std::vector<uint16_t> bx = parts2(sine(p.nx, g.Mx, true)), by = parts2(sine(p.ny, g.My, true));
     if (int e = dalloc(H, &H->SxBF, bx.size())) return e;
     if (int e = dalloc(H, &H->SyBF, by.size())) return e;
     KKT_HIP(hipMemcpy(H->SxBF, bx.data(), bx.size() * 2, hipMemcpyHostToDevice));
@@ -832,7 +859,7 @@ int kkt_spatial_solve(kktdd_handle* H, const double* b, double* x, int32_t nslic
     const double sy = std::sin(M_PI * (q + 1) / (2.0 * p.ny));
     for (int a = 0; a < g.mx; ++a) {
       const double sx = std::sin(M_PI * (a + 1) / (2.0 * p.nx));
-      inv[(size_t)q * g.Mx + a] =
+      inv[(size_t)mode_pos(q, g.My) * g.Mx + mode_pos(a, g.Mx)] =
           norm / (shift + dtnu * 4.0 / (dx * dx) * sx * sx + dtnu * 4.0 / (dy * dy) * sy * sy);
     }
   }

@@ -50,7 +50,9 @@ k_coarse_factor(Geom g, const double* __restrict__ G2, const double* __restrict_
   const int mode = blockIdx.x * kBlock + threadIdx.x;
   const int nmodes = g.nxy;
   if (mode >= nmodes) return;
-  const int q = mode / g.mx, p = mode % g.mx;
+  // mode enumeration shared with k_coarse_solve: the live positions of the padded mode space
+  const int q = mode_at(live_pos(mode / g.mx, g.my, g.My), g.My);
+  const int p = mode_at(live_pos(mode % g.mx, g.mx, g.Mx), g.Mx);
   const double d = g.sigma + lamy[q] + lamx[p];   // tables hold dt*nu*lambda
   const int hb = 2 * g.nb - 1, w = hb + 1;
   const double invh = 1.0 / g.h;
@@ -88,9 +90,8 @@ k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat
   const int mode = blockIdx.x * 64 + threadIdx.x;
   const int nmodes = g.nxy;
   if (mode >= nmodes) return;
-  const int q = mode / g.mx, p = mode % g.mx;
   const long long MM = g.padded();
-  double* x = xhat + (long long)q * g.Mx + p;
+  double* x = xhat + (long long)live_pos(mode / g.mx, g.my, g.My) * g.Mx + live_pos(mode % g.mx, g.mx, g.Mx);
   const double* Lm = fac + mode;
   const long long ld = nmodes;
   const int nc = g.nc;

@@ -4,7 +4,7 @@
 // the 2-D discrete sine transform,
 //     D^{-1} b = (4/(nx ny)) S_y [ (S_y b S_x) ./ (shift + dt*nu*(lam^y_q + lam^x_p)) ] S_x,
 // with S_x[p][i] = sin(pi (p+1)(i+1)/nx) symmetric and S_x S_x = (nx/2) I.  The 4/(nx ny)
-// factor is folded into the inverse eigenvalue table.  A solve is four dense GEMMs.
+// factor is folded into the inverse eigenvalue table.  A solve is four sine-transform products.
 //
 // Work split.  A slice b is (my x mx), rows = y.  Right products (. S_x) only mix within a
 // row, left products (S_y .) only within a column.  A solve is therefore arranged as
@@ -13,7 +13,16 @@
 //     row kernel:    y  = U S_x                               (row blocks of 16)
 // and in a sweep the last row product of step j and the first of step j+1 run in the same
 // row kernel (b_{j+1} = r'_{j+1} + y_j is formed row-locally), so one step costs one row and
-// one column launch, each doing two chained 16 x M x M GEMMs.
+// one column launch, each doing two chained products.
+//
+// Folding.  With n = m+1 intervals, S[p][n-i] = (-1)^(p+1) S[p][i] (1-based p, i).  A forward
+// transform therefore takes the sums b_i + b_{n-i} (i <= n/2, the middle point once) to the
+// odd frequencies and the differences b_i - b_{n-i} to the even ones, through two half-size
+// blocks F_odd[k][j] = sin(pi (2j+1)(k+1)/n) and F_even[k][j] = sin(pi (2j+2)(k+1)/n); an
+// inverse transform computes E = F_odd x_odd and O = F_even x_even and writes E + O at point i
+// and E - O at point n-i.  Each 1-D transform costs half the multiply-adds of the dense one.
+// Mode space keeps the odd frequencies in the first half of the padded extent and the even
+// ones in the second (mode_pos).
 //
 // GEMM engines (one per arithmetic):
 //   f64, f32      16x16x4 MFMA.  Lane l supplies A[l%16][l/16] and B[l/16][l%16]; accumulator
@@ -24,9 +33,9 @@
 //                 rounded remainder of the previous ones) and a product is accumulated from
 //                 the part products a0b0 (x1); a0b0 + a0b1 + a1b0 (x3); and those plus
 //                 a0b2 + a1b1 + a2b0 (x6) (Henry, Tang, Heinecke, ARITH 2019).
-// All layouts were checked on gfx950.  The sine matrices (pre-split into bf16 parts for the
-// bf16 engines) are read straight from L2 using their symmetry, so every operand load is a
-// run of contiguous row segments; the other operand sits in LDS.  Work buffers are float64
+// All layouts were checked on gfx950.  The half-size blocks (pre-split into bf16 parts for the
+// bf16 engines) are read straight from L2, stored in whichever orientation makes every
+// operand load a run of contiguous row segments; the other operand sits in LDS.  Work buffers are float64
 // for the f64 engine and float32 otherwise.
 #include <algorithm>
 #include <array>
@@ -60,8 +69,9 @@ __device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
 }
 
 // Work split inside a workgroup: the M/16 column (or row) tiles of a 16-wide block are dealt
-// to nw waves, TPW tiles each, with nw * TPW == M/16 exactly (the padded extents are chosen so
-// that this holds).  The sine-matrix operand comes from L2 through a register ring that runs
+// to nw waves (nw even), TPW tiles each, with nw * TPW == M/16 exactly (the padded extents
+// are chosen so that this holds).  Even waves take tiles of the odd-frequency half, odd waves
+// tiles of the even-frequency half, so every wave's tiles share one half of the operand.  The sine-matrix operand comes from L2 through a register ring that runs
 // ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.  The ring is
 // PD k-steps deep: 4 by default, deeper (16 for one tile per wave, 8 for two to four) where
 // the autotuner measured it faster.
@@ -70,13 +80,23 @@ template <int TPW>
 constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
 
 // ---- plain engines (f64, f32) ----------------------------------------------------------
+// A half-transform table Q holds two H x H blocks (H = M/2), block b at Q + b*H*H, row-major.
+// gemm_right: acc[t] += A(:, half blk) * Q[blk](:, tile),  A = 16 x M operand in LDS.
+// gemm_left:  acc[t] += Q[blk](:, tile)^T * B(half blk, :), B = M x 16 operand in LDS.
+// Output tile t of a wave is local tile lt0 + t*lts of half blk.
 template <typename T>
 struct EngPlain {
   using data_t = T;
   using acc_t = typename AccT<T>::type;
   using s_t = T;
+  static constexpr int kTableParts = 1;
   static __host__ __device__ size_t rows_lds(int M) { return (size_t)16 * (M + 1) * sizeof(T); }
   static __host__ __device__ size_t cols_lds(int M) { return (size_t)M * 17 * sizeof(T); }
+  // The combine buffer of the inverse products is the operand buffer itself, in the same
+  // layout, so a thread may overwrite the combine values it has just read.
+  static constexpr bool kCombInPlace = true;
+  static __host__ __device__ size_t rows_lds_total(int M) { return rows_lds(M); }
+  static __host__ __device__ size_t cols_lds_total(int M) { return cols_lds(M); }
   static __device__ int acc_row(int lk, int r) {
     if constexpr (sizeof(T) == 8) return lk + 4 * r; else return 4 * lk + r;
   }
@@ -89,66 +109,65 @@ struct EngPlain {
     (void)M;
     reinterpret_cast<T*>(lds)[k * 17 + c] = v;
   }
-  // acc[t] += A (16 x M) * S(:, tile wave + t*nw), S symmetric M x M.
   template <int TPW, int kPD>
-  static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ S, int M,
-                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
-    const T* A = reinterpret_cast<const T*>(lds);
-    const int lda = M + 1;
-    const T* Sp = S + (long long)lk * M + wave * 16 + li;
-    const long long tstride = (long long)nw * 16;
-    const int nks = M >> 2;
+  static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    const int H = M >> 1;
+    const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
+    const T* Sp = Q + (long long)blk * H * H + (long long)lk * H + lt0 * 16 + li;
+    const long long tstride = (long long)lts * 16;
+    const int nks = H >> 2;
     T bq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
       if (p < nks) {
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * H + t * tstride];
       }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
       for (int p = 0; p < kPD; ++p) {
         const int ks = ks0 + p;
         if (ks >= nks) break;
-        const T a = A[li * lda + 4 * ks + lk];
+        const T a = Ab[4 * ks];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
         const int kn = ks + kPD;
         if (kn < nks) {
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+          for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * H + t * tstride];
         }
       }
     }
   }
-  // acc[t] += S(row tile wave + t*nw, :) * B (M x 16).
   template <int TPW, int kPD>
-  static __device__ void gemm_left(const T* __restrict__ S, const unsigned char* lds, int M,
-                                   int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
-    const T* B = reinterpret_cast<const T*>(lds);
-    // A(row = li, k = lk) of tile rt is S[rt*16 + li][k0 + lk] = S[k0 + lk][rt*16 + li].
-    const T* Sp = S + (long long)lk * M + wave * 16 + li;
-    const long long tstride = (long long)nw * 16;
-    const int nks = M >> 2;
+  static __device__ void gemm_left(const T* __restrict__ Q, const unsigned char* lds, int M,
+                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    const int H = M >> 1;
+    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
+    // A(row = li, k = lk) of local tile lt is Q[blk][k][lt*16 + li]
+    const T* Sp = Q + (long long)blk * H * H + (long long)lk * H + lt0 * 16 + li;
+    const long long tstride = (long long)lts * 16;
+    const int nks = H >> 2;
     T aq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
       if (p < nks) {
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * M + t * tstride];
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * H + t * tstride];
       }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
       for (int p = 0; p < kPD; ++p) {
         const int ks = ks0 + p;
         if (ks >= nks) break;
-        const T b = B[(4 * ks + lk) * 17 + li];
+        const T b = Bb[4 * ks * 17];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
         const int kn = ks + kPD;
         if (kn < nks) {
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * M + t * tstride];
+          for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * H + t * tstride];
         }
       }
     }
@@ -156,14 +175,29 @@ struct EngPlain {
 };
 
 // ---- split-bfloat16 engines -------------------------------------------------------------
+// Tables hold three bfloat16 parts, part p at offset p*M*M/2 (two H x H blocks each).  Here
+// gemm_right reads Q[blk](tile, :) and gemm_left Q[blk](tile, :) as well (k contiguous, 16
+// bytes per lane), so these engines take the transposes of the plain engines' tables.
 template <int SPLIT>
 struct EngBF {
   static constexpr int NP = SPLIT == 1 ? 1 : (SPLIT == 3 ? 2 : 3);   // parts per operand
   using data_t = float;
   using acc_t = v4f;
-  using s_t = __bf16;    // NP parts of an M x M matrix, part p at offset p*M*M
+  using s_t = __bf16;
+  static constexpr int kTableParts = 3;
   static __host__ __device__ size_t rows_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
   static __host__ __device__ size_t cols_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
+  // The float combine buffers ([16][M+1] rows, [M][17] cols) overlap the operand parts, so
+  // every combine value is read before the operand is written again.
+  static constexpr bool kCombInPlace = false;
+  static __host__ __device__ size_t rows_lds_total(int M) {
+    const size_t c = (size_t)16 * (M + 1) * 4;
+    return rows_lds(M) > c ? rows_lds(M) : c;
+  }
+  static __host__ __device__ size_t cols_lds_total(int M) {
+    const size_t c = (size_t)M * 17 * 4;
+    return cols_lds(M) > c ? cols_lds(M) : c;
+  }
   static __device__ int acc_row(int lk, int r) { return 4 * lk + r; }
   static __device__ void split(float v, __bf16 (&part)[NP]) {
     part[0] = (__bf16)v;
@@ -202,27 +236,28 @@ struct EngBF {
     return mfma_bf(a[0], b[0], acc);
   }
   static constexpr int ring(int TPW) { return TPW * NP <= 8 ? 2 : 1; }
-  // acc[t] += A (16 x M) * S(:, tile wave + t*nw); the B fragment of tile ct is
-  // S[32ks + 8lk + i][ct*16 + li] = S[ct*16 + li][32ks + 8lk + i]: 16 contiguous bytes.
+  // fragment of local tile lt at k-step ks: Q_p[blk][lt*16 + li][32ks + 8lk .. +8]
+  static __device__ bf16x8 qload(const __bf16* __restrict__ Q, int M, int blk, int lt, int ks,
+                                 int p, int li, int lk) {
+    const int H = M >> 1;
+    const long long row = (long long)lt * 16 + li;
+    return *reinterpret_cast<const bf16x8*>(Q + (long long)p * M * H + (long long)blk * H * H +
+                                            row * H + 32 * ks + 8 * lk);
+  }
   template <int TPW, int PD_unused>
-  static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ S, int M,
-                                    int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+  static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ Q, int M,
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     constexpr int RD = ring(TPW);
-    const __bf16* A = reinterpret_cast<const __bf16*>(lds);
-    const long long MM = (long long)M * M;
-    const int lda = M + 8;
-    auto bload = [&](int ks, int t, int p) {
-      const long long row = (long long)(wave + t * nw) * 16 + li;
-      return *reinterpret_cast<const bf16x8*>(S + p * MM + row * M + 32 * ks + 8 * lk);
-    };
+    const int H = M >> 1, lda = M + 8;
+    const __bf16* A = reinterpret_cast<const __bf16*>(lds) + blk * H + 8 * lk;
     bf16x8 bq[RD][TPW][NP];
+    const int nks = H >> 5;
 #pragma unroll
     for (int d = 0; d < RD; ++d)
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) bq[d][t][p] = bload(d, t, p);
-    const int nks = M >> 5;
+        for (int p = 0; p < NP; ++p) bq[d][t][p] = d < nks ? qload(Q, M, blk, lt0 + t * lts, d, p, li, lk) : bf16x8{};
     for (int ks0 = 0; ks0 < nks; ks0 += RD) {
 #pragma unroll
       for (int d = 0; d < RD; ++d) {
@@ -231,7 +266,7 @@ struct EngBF {
         bf16x8 af[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
-          af[p] = *reinterpret_cast<const bf16x8*>(A + (p * 16 + li) * lda + 32 * ks + 8 * lk);
+          af[p] = *reinterpret_cast<const bf16x8*>(A + (p * 16 + li) * lda + 32 * ks);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mma(af, bq[d][t], acc[t]);
         const int kn = ks + RD;
@@ -239,31 +274,25 @@ struct EngBF {
 #pragma unroll
           for (int t = 0; t < TPW; ++t)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) bq[d][t][p] = bload(kn, t, p);
+            for (int p = 0; p < NP; ++p) bq[d][t][p] = qload(Q, M, blk, lt0 + t * lts, kn, p, li, lk);
         }
       }
     }
   }
-  // acc[t] += S(row tile wave + t*nw, :) * B (M x 16, stored transposed in LDS).
   template <int TPW, int PD_unused>
-  static __device__ void gemm_left(const __bf16* __restrict__ S, const unsigned char* lds, int M,
-                                   int wave, int nw, int li, int lk, acc_t (&acc)[TPW]) {
+  static __device__ void gemm_left(const __bf16* __restrict__ Q, const unsigned char* lds, int M,
+                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     constexpr int RD = ring(TPW);
-    const __bf16* Bt = reinterpret_cast<const __bf16*>(lds);
-    const long long MM = (long long)M * M;
-    const int ldb = M + 8;
-    auto aload = [&](int ks, int t, int p) {
-      const long long row = (long long)(wave + t * nw) * 16 + li;
-      return *reinterpret_cast<const bf16x8*>(S + p * MM + row * M + 32 * ks + 8 * lk);
-    };
+    const int H = M >> 1, ldb = M + 8;
+    const __bf16* Bt = reinterpret_cast<const __bf16*>(lds) + blk * H + 8 * lk;
     bf16x8 aq[RD][TPW][NP];
+    const int nks = H >> 5;
 #pragma unroll
     for (int d = 0; d < RD; ++d)
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int p = 0; p < NP; ++p) aq[d][t][p] = aload(d, t, p);
-    const int nks = M >> 5;
+        for (int p = 0; p < NP; ++p) aq[d][t][p] = d < nks ? qload(Q, M, blk, lt0 + t * lts, d, p, li, lk) : bf16x8{};
     for (int ks0 = 0; ks0 < nks; ks0 += RD) {
 #pragma unroll
       for (int d = 0; d < RD; ++d) {
@@ -272,7 +301,7 @@ struct EngBF {
         bf16x8 bf[NP];
 #pragma unroll
         for (int p = 0; p < NP; ++p)
-          bf[p] = *reinterpret_cast<const bf16x8*>(Bt + (p * 16 + li) * ldb + 32 * ks + 8 * lk);
+          bf[p] = *reinterpret_cast<const bf16x8*>(Bt + (p * 16 + li) * ldb + 32 * ks);
 #pragma unroll
         for (int t = 0; t < TPW; ++t) acc[t] = mma(aq[d][t], bf, acc[t]);
         const int kn = ks + RD;
@@ -280,7 +309,7 @@ struct EngBF {
 #pragma unroll
           for (int t = 0; t < TPW; ++t)
 #pragma unroll
-            for (int p = 0; p < NP; ++p) aq[d][t][p] = aload(kn, t, p);
+            for (int p = 0; p < NP; ++p) aq[d][t][p] = qload(Q, M, blk, lt0 + t * lts, kn, p, li, lk);
         }
       }
     }
@@ -288,14 +317,16 @@ struct EngBF {
 };
 
 // ---- row kernel ------------------------------------------------------------------------
-// One workgroup = 16 rows of one slice.  Optional GEMM1 (y = g1_scale * U S_x) with its
-// epilogue stores, then optional formation of b and GEMM2 (T = b S_x).
+// One workgroup = 16 rows of one slice.  Optional GEMM1 (inverse product y = g1_scale * U S_x,
+// U in x-mode space) with its epilogue stores, then optional formation of b and GEMM2
+// (forward product T = b S_x, T in x-mode space).  Both products are folded: the workgroup
+// works on mirrored column pairs (c, mx-1-c), 2*TPW pairs per thread.
 enum BMode { B_NONE = 0, B_RPRIME_PLUS_Y = 1, B_H_YBUF_PLUS_Y = 2, B_H_Y = 3, B_INPUT = 4 };
 enum OutMode { OUT_NONE = 0, OUT_OWNED = 1, OUT_PLAIN = 2 };
 
 template <typename T>
 struct RowArgs {
-  const void* Sx;            // engine's sine-matrix operand
+  const void* Sx;            // engine's half-transform tables of x: forward, then inverse
   const T* g1_in;            // padded slices (nullptr: y = 0)
   long long g1_stride;
   double g1_scale;
@@ -315,131 +346,166 @@ struct RowArgs {
   long long g2_stride;
 };
 
+template <typename Eng>
+__device__ inline const typename Eng::s_t* table(const void* S, int M, int inverse) {
+  return static_cast<const typename Eng::s_t*>(S) +
+         (inverse ? (long long)Eng::kTableParts * M * (M >> 1) : 0);
+}
+
 template <typename Eng, int TPW, int PD>
 __global__ void __launch_bounds__(512)
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
-  using S_t = typename Eng::s_t;
   extern __shared__ unsigned char smem_raw[];
-  const int Mx = g.Mx;
-  const S_t* Sx = static_cast<const S_t*>(a.Sx);
+  const int Mx = g.Mx, Hx = Mx >> 1, mx = g.mx, Ax = (mx + 1) / 2, ldc = Mx + 1;
   const int rb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
+  T* comb = reinterpret_cast<T*>(smem_raw);
+  constexpr int NPR = 2 * TPW;   // 16 rows x Hx pairs = NPR * blockDim.x
   acc_t acc[TPW];
-#pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
 
   // node of a sweep step in this subdomain (0-based subdomain s): first = s*k + 1 - delta
   const int first = s * g.k + 1 - g.delta;
 
-  // Right-hand-side operands of b, fetched before GEMM1 so their latency hides behind it.
-  T pre[TPW][4];
+  // Right-hand-side operands of b at both points of every pair, fetched before GEMM1 so their
+  // latency hides behind it.
+  T pre[NPR][2];
   if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
     const int bnode = first + a.b_step;
     const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int col = (wave + t * nw) * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rb * 16 + Eng::acc_row(lk, r);
-        const bool in = row < g.my && col < g.mx;
-        T v = 0;
+    for (int i = 0; i < NPR; ++i) {
+      const int e = threadIdx.x + i * nthr;
+      const int r = e / Hx, k = e - r * Hx;
+      const int row = rb * 16 + r;
+      T v1 = 0, v2 = 0;
+      if (row < g.my && k < Ax) {
+        const int c2 = mx - 1 - k;
         if (a.b_mode == B_RPRIME_PLUS_Y) {
-          if (in && bnode >= 1) v = (T)a.rin[(long long)(bnode - 1) * g.nxy + row * g.mx + col];
+          if (bnode >= 1) {
+            const double* src = a.rin + (long long)(bnode - 1) * g.nxy + (long long)row * mx;
+            v1 = (T)src[k];
+            v2 = (T)src[c2];
+          }
         } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
-          v = a.ybuf_in[s * a.ybuf_stride + (long long)row * Mx + col];
-        } else if (in) {
-          v = (T)(isc * a.rin[(long long)s * g.nxy + row * g.mx + col]);
+          const T* src = a.ybuf_in + s * a.ybuf_stride + (long long)row * Mx;
+          v1 = src[k];
+          v2 = src[c2];
+        } else {
+          const double* src = a.rin + (long long)s * g.nxy + (long long)row * mx;
+          v1 = (T)(isc * src[k]);
+          v2 = (T)(isc * src[c2]);
         }
-        pre[t][r] = v;
       }
+      pre[i][0] = v1;
+      pre[i][1] = v2;
     }
   }
 
-  // ---- GEMM1: y = U S_x ------------------------------------------------------------------
+  // ---- GEMM1: E | O = U(odd modes) F_odd^T | U(even modes) F_even^T, into the combine buffer
   if (a.g1_in) {
     const T* src = a.g1_in + s * a.g1_stride + (long long)rb * 16 * Mx;
-    for (int e = threadIdx.x; e < 16 * Mx; e += nthr) Eng::put_a(smem_raw, Mx, e / Mx, e % Mx, src[e]);
+    const int live_rows = g.my - rb * 16;   // rows at or past it are padding: read as zero
+    for (int e = threadIdx.x; e < 16 * Mx; e += nthr) {
+      const int r = e / Mx;
+      Eng::put_a(smem_raw, Mx, r, e - r * Mx, r < live_rows ? src[e] : (T)0);
+    }
     __syncthreads();
-    Eng::template gemm_right<TPW, PD>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
+    Eng::template gemm_right<TPW, PD>(smem_raw, table<Eng>(a.Sx, Mx, 1), Mx, blk, lt0, lts, li, lk, acc);
+    __syncthreads();  // every wave has read the operand, which the combine buffer overlays
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[t][r] = (T)(acc[t][r] * a.g1_scale);
+      for (int r = 0; r < 4; ++r)
+        comb[Eng::acc_row(lk, r) * ldc + blk * Hx + (lt0 + t * lts) * 16 + li] = (T)(acc[t][r] * a.g1_scale);
+    __syncthreads();
   }
 
-  // ---- GEMM1 epilogue stores -------------------------------------------------------------
-  if (a.g1_in) {
-    const int node = first + a.g1_step;
-    const bool owned = a.g1_step >= g.delta;
+  // ---- per pair: y at both points (E +- O), its stores, and the folded b (sum | difference)
+  const bool form_b = a.b_mode != B_NONE;
+  const bool owned = a.g1_step >= g.delta;
+  const int node = first + a.g1_step;
+  const T hT = (T)g.h;
+  auto store_y = [&](int row, int col, T v) {
+    if (a.ystore) a.ystore[s * a.ystore_stride + (long long)row * Mx + col] = v;
+    const long long pt = (long long)row * mx + col;
+    if (a.out_mode == OUT_PLAIN) {
+      double val = (double)v;
+      if (a.c0) {   // slice s is time-node s+1 of a field: add the prolonged coarse part
+        const int n = s + 1, sd = s / g.k;
+        const double* c = a.c0 + (long long)(g.nb * sd) * g.nxy + pt;
+        val += c[0];
+        if (g.nb == 2) val += (-1.0 + 2.0 * (double)(n - sd * g.k) / g.k) * c[g.nxy];
+      }
+      a.out64[(long long)s * g.nxy + pt] = val;
+    } else if (a.out_mode == OUT_OWNED && owned) {
+      double val = (double)v;
+      if (a.c0) {
+        const double* c = a.c0 + (long long)(g.nb * s) * g.nxy + pt;
+        val += c[0];
+        if (g.nb == 2) val += (-1.0 + 2.0 * (double)(node - s * g.k) / g.k) * c[g.nxy];
+      }
+      a.out64[(long long)(node - 1) * g.nxy + pt] = val;
+    }
+  };
+  T yv[NPR][2];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int col = (wave + t * nw) * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = rb * 16 + Eng::acc_row(lk, r);
-        const T v = acc[t][r];
-        if (a.ystore) a.ystore[s * a.ystore_stride + (long long)row * Mx + col] = v;
-        if (row < g.my && col < g.mx) {
-          if (a.out_mode == OUT_PLAIN) {
-            double val = (double)v;
-            if (a.c0) {   // slice s is time-node s+1 of a field: add the prolonged coarse part
-              const int n = s + 1, sd = s / g.k;
-              const double* c = a.c0 + (long long)(g.nb * sd) * g.nxy + row * g.mx + col;
-              val += c[0];
-              if (g.nb == 2) val += (-1.0 + 2.0 * (double)(n - sd * g.k) / g.k) * c[g.nxy];
-            }
-            a.out64[(long long)s * g.nxy + row * g.mx + col] = val;
-          } else if (a.out_mode == OUT_OWNED && owned) {
-            const long long pt = row * g.mx + col;
-            double val = (double)v;
-            if (a.c0) {
-              const double* c = a.c0 + (long long)(g.nb * s) * g.nxy + pt;
-              val += c[0];
-              if (g.nb == 2) val += (-1.0 + 2.0 * (double)(node - s * g.k) / g.k) * c[g.nxy];
-            }
-            a.out64[(long long)(node - 1) * g.nxy + pt] = val;
-          }
-        }
+  for (int i = 0; i < NPR; ++i) {
+    const int e = threadIdx.x + i * nthr;
+    const int r = e / Hx, k = e - r * Hx;
+    const int row = rb * 16 + r;
+    const int c2 = mx - 1 - k;
+    T y1 = 0, y2 = 0;
+    if (a.g1_in) {
+      const T E = comb[r * ldc + k], O = comb[r * ldc + Hx + k];
+      y1 = E + O;
+      y2 = E - O;
+      if (k < Ax && row < g.my) {
+        store_y(row, k, y1);
+        if (k != c2) store_y(row, c2, y2);
       }
     }
+    yv[i][0] = y1;
+    yv[i][1] = y2;
   }
-  if (a.b_mode == B_NONE) return;
-
-  // ---- form b (row-local) into LDS -------------------------------------------------------
-  __syncthreads();  // every wave has finished reading the LDS operand of GEMM1
-  {
-    const T hT = (T)g.h;
+  if (!form_b) return;
+  if constexpr (!Eng::kCombInPlace) __syncthreads();   // combine values read before the operand is written
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-      const int col = (wave + t * nw) * 16 + li;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int rloc = Eng::acc_row(lk, r);
-        T b = 0;
-        switch (a.b_mode) {
-          case B_RPRIME_PLUS_Y: b = pre[t][r] + (T)acc[t][r]; break;
-          case B_H_YBUF_PLUS_Y: b = hT * pre[t][r] + (T)acc[t][r]; break;
-          case B_H_Y: b = hT * (T)acc[t][r]; break;
-          case B_INPUT: b = pre[t][r]; break;
-        }
-        Eng::put_a(smem_raw, Mx, rloc, col, b);
-      }
+  for (int i = 0; i < NPR; ++i) {
+    const int e = threadIdx.x + i * nthr;
+    const int r = e / Hx, k = e - r * Hx;
+    const bool mid = k == mx - 1 - k;
+    const T y1 = yv[i][0], y2 = yv[i][1];
+    T b1 = 0, b2 = 0;
+    switch (a.b_mode) {
+      case B_RPRIME_PLUS_Y: b1 = pre[i][0] + y1; b2 = pre[i][1] + y2; break;
+      case B_H_YBUF_PLUS_Y: b1 = hT * pre[i][0] + y1; b2 = hT * pre[i][1] + y2; break;
+      case B_H_Y: b1 = hT * y1; b2 = hT * y2; break;
+      case B_INPUT: b1 = pre[i][0]; b2 = pre[i][1]; break;
     }
+    T sum = 0, dif = 0;
+    if (k < Ax) {
+      sum = mid ? b1 : b1 + b2;
+      dif = mid ? (T)0 : b1 - b2;
+    }
+    Eng::put_a(smem_raw, Mx, r, k, sum);
+    Eng::put_a(smem_raw, Mx, r, Hx + k, dif);
   }
   __syncthreads();
 
-  // ---- GEMM2: T = b S_x ------------------------------------------------------------------
+  // ---- GEMM2: T = [sums | differences] (F_odd | F_even), stored in x-mode order -------------
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  Eng::template gemm_right<TPW, PD>(smem_raw, Sx, Mx, wave, nw, li, lk, acc);
+  Eng::template gemm_right<TPW, PD>(smem_raw, table<Eng>(a.Sx, Mx, 0), Mx, blk, lt0, lts, li, lk, acc);
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
-    const int col = (wave + t * nw) * 16 + li;
+    const int col = blk * Hx + (lt0 + t * lts) * 16 + li;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = rb * 16 + Eng::acc_row(lk, r);
@@ -449,15 +515,18 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
 }
 
 // ---- column kernel ---------------------------------------------------------------------
-// One workgroup = 16 columns of one slice: X = S_y T (optionally ./ lambda), and optionally
-// U = S_y X chained through LDS.
+// One workgroup = 16 columns of one slice.  fold: the input rows are points and the first
+// product is the forward transform X = S_y T (optionally ./ lambda); otherwise the input rows
+// are y-modes.  two: the inverse product U = S_y X follows, chained through LDS.  An inverse
+// last product writes point rows (mirrored pairs combined); a forward one writes mode rows.
 template <typename T>
 struct ColArgs {
-  const void* Sy;      // engine's sine-matrix operand
+  const void* Sy;      // engine's half-transform tables of y: forward, then inverse
   const T* in;
   long long in_stride;
   const T* invlam;     // nullptr: no scaling
-  int two;             // chain the second product
+  int fold;            // input rows are points (forward first product)
+  int two;             // chain the inverse product (needs fold)
   T* out;
   long long out_stride;
 };
@@ -467,48 +536,89 @@ __global__ void __launch_bounds__(512)
 k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
-  using S_t = typename Eng::s_t;
   extern __shared__ unsigned char smem_raw[];
-  const int Mx = g.Mx, My = g.My;
-  const S_t* Sy = static_cast<const S_t*>(a.Sy);
+  const int Mx = g.Mx, My = g.My, Hy = My >> 1, my = g.my, Ay = (my + 1) / 2;
   const int cb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
+  T* comb = reinterpret_cast<T*>(smem_raw);
 
   const T* src = a.in + s * a.in_stride + cb * 16;
-  for (int e = threadIdx.x; e < My * 16; e += nthr)
-    Eng::put_b(smem_raw, My, e >> 4, e & 15, src[(long long)(e >> 4) * Mx + (e & 15)]);
+  if (a.fold) {
+    for (int e = threadIdx.x; e < Hy * 16; e += nthr) {
+      const int k = e >> 4, c = e & 15;
+      T sum = 0, dif = 0;
+      if (k < Ay) {
+        const int r2 = my - 1 - k;
+        const T v1 = src[(long long)k * Mx + c];
+        if (r2 == k) {
+          sum = v1;
+        } else {
+          const T v2 = src[(long long)r2 * Mx + c];
+          sum = v1 + v2;
+          dif = v1 - v2;
+        }
+      }
+      Eng::put_b(smem_raw, My, k, c, sum);
+      Eng::put_b(smem_raw, My, Hy + k, c, dif);
+    }
+  } else {
+    for (int e = threadIdx.x; e < My * 16; e += nthr)
+      Eng::put_b(smem_raw, My, e >> 4, e & 15, src[(long long)(e >> 4) * Mx + (e & 15)]);
+  }
   __syncthreads();
 
   acc_t acc[TPW];
-  for (int pass = 0; pass < 1 + a.two; ++pass) {
+  const int npass = 1 + a.two;
+  for (int pass = 0; pass < npass; ++pass) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    Eng::template gemm_left<TPW, PD>(Sy, smem_raw, My, wave, nw, li, lk, acc);
+    const int inverse = !(pass == 0 && a.fold);
+    Eng::template gemm_left<TPW, PD>(table<Eng>(a.Sy, My, inverse), smem_raw, My, blk, lt0, lts, li, lk, acc);
     if (pass == 0 && a.invlam) {
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          acc[t][r] *= a.invlam[(long long)((wave + t * nw) * 16 + Eng::acc_row(lk, r)) * Mx + cb * 16 + li];
+          acc[t][r] *= a.invlam[(long long)(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * Mx +
+                                cb * 16 + li];
     }
-    if (pass == 0 && a.two) {
+    if (pass + 1 < npass) {
       __syncthreads();
 #pragma unroll
       for (int t = 0; t < TPW; ++t)
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          Eng::put_b(smem_raw, My, (wave + t * nw) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
+          Eng::put_b(smem_raw, My, blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
       __syncthreads();
     }
   }
   T* dst = a.out + s * a.out_stride + cb * 16;
+  if (a.fold && !a.two) {   // forward only: y-mode rows
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        dst[(long long)(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * Mx + li] = (T)acc[t][r];
+    return;
+  }
+  // inverse last: E (odd modes) and O (even modes) of each pair through LDS, then the points
+  __syncthreads();  // every wave has read the operand, which the combine buffer overlays
 #pragma unroll
   for (int t = 0; t < TPW; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-      dst[(long long)((wave + t * nw) * 16 + Eng::acc_row(lk, r)) * Mx + li] = (T)acc[t][r];
+      comb[(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * 17 + li] = (T)acc[t][r];
+  __syncthreads();
+  for (int e = threadIdx.x; e < Ay * 16; e += nthr) {
+    const int k = e >> 4, c = e & 15;
+    const T E = comb[k * 17 + c], O = comb[(Hy + k) * 17 + c];
+    const int r2 = my - 1 - k;
+    dst[(long long)k * Mx + c] = E + O;
+    if (r2 != k) dst[(long long)r2 * Mx + c] = E - O;
+  }
 }
 
 // ---- launch helpers ----------------------------------------------------------------------
@@ -591,29 +701,36 @@ int allow_lds(F* kernel, size_t lds) {
   return 0;
 }
 
-// Algorithmic flops of one launch: 2*my*mx*mx per right product, 2*my*my*mx per left product.
+// Flops of the folded products: a 1-D transform of extent m costs 2*(A^2 + B^2) per vector,
+// A = ceil(m/2), B = floor(m/2) (about half of the unfolded 2*m^2).
+inline double folded_flops(int m) {
+  const double A = (m + 1) / 2, B = m / 2;
+  return 2.0 * (A * A + B * B);
+}
+
 template <typename Eng, int TPW, int PD>
 int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
-  const size_t lds = Eng::rows_lds(g.Mx);
+  const size_t lds = Eng::rows_lds_total(g.Mx);
   if (int e = allow_lds(k_rows<Eng, TPW, PD>, lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), dim3(g.My / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  // row blocks past the interior would only write padding rows, which nothing reads
+  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), dim3((g.my + 15) / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
-  prof_end(kclass, s, 0.0, 2.0 * ngemm * nslices * (double)g.my * g.mx * g.mx);
+  prof_end(kclass, s, 0.0, ngemm * nslices * (double)g.my * folded_flops(g.mx));
   return 0;
 }
 
 template <typename Eng, int TPW, int PD>
 int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
-  const size_t lds = Eng::cols_lds(g.My);
+  const size_t lds = Eng::cols_lds_total(g.My);
   if (int e = allow_lds(k_cols<Eng, TPW, PD>, lds)) return e;
   prof_begin(kclass, s);
   hipLaunchKernelGGL((k_cols<Eng, TPW, PD>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
   KKT_HIP(hipGetLastError());
-  prof_end(kclass, s, 0.0, 2.0 * (1 + a.two) * nslices * (double)g.my * g.my * g.mx);
+  prof_end(kclass, s, 0.0, (1 + a.two) * nslices * (double)g.mx * folded_flops(g.my));
   return 0;
 }
 
@@ -677,7 +794,7 @@ int spatial_solve_t(const Geom& g, const void* Sx, const void* Sy, const void* i
   r1.g2_stride = MM;
   if (int e = rows<Eng>(g, r1, nslices, KKTDD_K_OTHER, s)) return e;
   ColArgs<T> c{Sy, static_cast<const T*>(w1), MM,
-               static_cast<const T*>(invlam), 1, static_cast<T*>(w2), MM};
+               static_cast<const T*>(invlam), 1, 1, static_cast<T*>(w2), MM};
   if (int e = cols<Eng>(g, c, nslices, KKTDD_K_OTHER, s)) return e;
   RowArgs<T> r2 = row_args<T>(Sx);
   r2.g1_in = static_cast<const T*>(w2);
@@ -702,7 +819,7 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
   T* Ybuf = static_cast<T*>(Yb);
   const long long ystride = (long long)g.L * MM;
   const int nd = g.nd, L = g.L;
-  ColArgs<T> c{Sy, Tbuf, MM, static_cast<const T*>(invlam), 1, Ubuf, MM};
+  ColArgs<T> c{Sy, Tbuf, MM, static_cast<const T*>(invlam), 1, 1, Ubuf, MM};
 
   // forward sweep: y_j = D^{-1}(r'_j + y_{j-1})
   for (int j = 0; j < L; ++j) {
@@ -773,7 +890,7 @@ int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* i
   r.g2_out = static_cast<T*>(tmp);
   r.g2_stride = MM;
   if (int e = rows<Eng>(g, r, nslices, KKTDD_K_SWEEP_ROWS, s)) return e;
-  ColArgs<T> c{Sy, static_cast<const T*>(tmp), MM, nullptr, 0,
+  ColArgs<T> c{Sy, static_cast<const T*>(tmp), MM, nullptr, 1, 0,
                static_cast<T*>(out), MM};
   return cols<Eng>(g, c, nslices, KKTDD_K_SWEEP_COLS, s);
 }
@@ -783,7 +900,7 @@ int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in,
                   double* out, int nslices, double norm, const double* c0, hipStream_t s) {
   using T = typename Eng::data_t;
   const long long MM = g.padded();
-  ColArgs<T> c{Sy, static_cast<const T*>(in), MM, nullptr, 0,
+  ColArgs<T> c{Sy, static_cast<const T*>(in), MM, nullptr, 0, 0,
                static_cast<T*>(tmp), MM};
   if (int e = cols<Eng>(g, c, nslices, KKTDD_K_SWEEP_COLS, s)) return e;
   RowArgs<T> r = row_args<T>(Sx);
@@ -809,7 +926,7 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
   r.b_mode = B_H_Y;
   r.g2_out = static_cast<T*>(bufB);
   r.g2_stride = MM;
-  ColArgs<T> c{Sy, static_cast<const T*>(bufA), MM, static_cast<const T*>(invlam), 1,
+  ColArgs<T> c{Sy, static_cast<const T*>(bufA), MM, static_cast<const T*>(invlam), 1, 1,
                static_cast<T*>(bufB), MM};
   hipEvent_t e0, e1;
   KKT_HIP(hipEventCreate(&e0));
@@ -832,7 +949,7 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     int nc = 0;
     cand[nc++] = Shape{waves_for(M), 0};
     for (int nw : {2, 4, 8, t}) {
-      if (nw < 1 || nw > 8 || t % nw != 0 || t / nw > 8) continue;
+      if (nw < 2 || nw > 8 || (nw & 1) || t % nw != 0 || t / nw > 8) continue;
       for (int deep = 0; deep <= (t / nw <= 4 ? 1 : 0); ++deep) {
         bool seen = false;
         for (int i = 0; i < nc; ++i) seen = seen || (cand[i].nw == nw && cand[i].deep == deep);
@@ -936,14 +1053,14 @@ int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const d
   r.g2_out = tmp;
   r.g2_stride = MM;
   if (int e = rows<EngPlain<double>>(g, r, g.nc, KKTDD_K_COARSE, s)) return e;
-  ColArgs<double> c{Sy, tmp, MM, nullptr, 0, rhat, MM};
+  ColArgs<double> c{Sy, tmp, MM, nullptr, 1, 0, rhat, MM};
   return cols<EngPlain<double>>(g, c, g.nc, KKTDD_K_COARSE, s);
 }
 
 int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
                        double* c0, double* tmp, double norm, hipStream_t s) {
   const long long MM = g.padded();
-  ColArgs<double> c{Sy, chat, MM, nullptr, 0, tmp, MM};
+  ColArgs<double> c{Sy, chat, MM, nullptr, 0, 0, tmp, MM};
   if (int e = cols<EngPlain<double>>(g, c, g.nc, KKTDD_K_COARSE, s)) return e;
   RowArgs<double> r = row_args<double>(Sx);
   r.g1_in = tmp;
@@ -960,8 +1077,8 @@ namespace kktdd {
 
 int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep) {
   const int t = extent / 16;
-  if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 16 ||
-      extent % 16 != 0 || nslices < 1 || waves < 1 || waves > 8 || t % waves != 0 ||
+  if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 32 ||
+      extent % 32 != 0 || nslices < 1 || waves < 2 || waves > 8 || (waves & 1) || t % waves != 0 ||
       t / waves > 8 || deep < 0 || deep > 1)
     return set_error(KKTDD_EINVAL, "invalid launch shape");
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -971,7 +1088,7 @@ int tune_set(int kind, int precision, int extent, int nslices, int waves, int de
 }
 
 int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep) {
-  if (!waves || !deep || extent < 16 || extent % 16 != 0)
+  if (!waves || !deep || extent < 32 || extent % 32 != 0)
     return set_error(KKTDD_EINVAL, "invalid launch-shape query");
   const Shape sh = tuned_shape(kind, precision, extent, nslices);
   *waves = sh.nw;

@@ -14,8 +14,10 @@ namespace kktdd {
 // ---------------------------------------------------------------------------------------
 // Geometry of one problem, passed by value to kernels.
 // A slice is (ny-1) x (nx-1) interior points, x fastest.  Sine-transform work buffers pad
-// both extents up to multiples of 16 (Mx, My) so every MFMA tile is full; padded rows and
-// columns of the sine matrices and eigenvalue tables are zero, so padding stays zero.
+// both extents (Mx, My; pad_extent) so every MFMA tile is full.  Along a transformed extent
+// they hold sine modes in the folded order of mode_pos; along an untransformed one, the
+// interior points followed by padding.  The half-transform tables and the eigenvalue tables
+// are zero at padding positions, so padding modes stay zero; padding points are never read.
 // ---------------------------------------------------------------------------------------
 struct Geom {
   int mx, my;          // interior points per row / per column
@@ -39,15 +41,34 @@ struct Geom {
   __host__ __device__ long long padded() const { return (long long)Mx * My; }
 };
 
-// Padded sine-transform extent: a multiple of 16 whose tile count t = M/16 splits evenly over
-// the waves of a workgroup (t <= 8, or a multiple of 4 up to 32, or of 8 above).  The bfloat16
-// engines step k by 32, so for them t is also even.
-inline int pad_extent(int m, bool even = false) {
-  int t = (m + 15) / 16;
-  if (even && (t & 1)) ++t;
-  if (t > 8) t = (t + 3) / 4 * 4;
-  if (t > 32) t = (t + 7) / 8 * 8;
-  return 16 * t;
+// Padded sine-transform extent.  The transforms are folded by parity: with n = m + 1
+// intervals, sin(pi p (n-i)/n) = (-1)^(p+1) sin(pi p i/n), so mirrored points i and n-i enter
+// the odd frequencies as a sum and the even ones as a difference, and each 1-D transform
+// splits into two half-size products.  The padded extent M is twice a half extent H that holds
+// the A = ceil(m/2) sums (or odd frequencies) in [0, H) and the B = floor(m/2) differences (or
+// even frequencies) in [H, 2H).  H is a multiple of 16 (of 32 for the bfloat16 engines, which
+// step k by 32), and the tile count t = M/16 splits evenly over the waves of a workgroup with
+// every wave inside one half (t <= 8, or a multiple of 4 up to 32, or of 8 above).
+inline int pad_extent(int m, bool bf16 = false) {
+  int tb = ((m + 1) / 2 + 15) / 16;   // tiles per half
+  if (bf16 && (tb & 1)) ++tb;
+  if (2 * tb > 8) tb = (tb + 1) / 2 * 2;
+  if (2 * tb > 32) tb = (tb + 3) / 4 * 4;
+  return 32 * tb;
+}
+
+// Sine mode a (0-based; frequency a+1) sits at position mode_pos(a, M) of a padded extent M:
+// odd frequencies in the first half, even ones in the second.  mode_at inverts it; a position
+// whose mode_at is >= m is padding.
+__host__ __device__ inline int mode_pos(int a, int M) { return (a & 1) * (M >> 1) + (a >> 1); }
+__host__ __device__ inline int mode_at(int pos, int M) {
+  const int H = M >> 1;
+  return pos < H ? 2 * pos : 2 * (pos - H) + 1;
+}
+// The j-th non-padding position (j < m), in increasing order.
+__host__ __device__ inline int live_pos(int j, int m, int M) {
+  const int A = (m + 1) / 2;
+  return j < A ? j : (M >> 1) + (j - A);
 }
 
 // Launch helpers report through this; the host driver converts to KKTDD_EHIP.

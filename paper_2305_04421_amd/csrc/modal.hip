@@ -126,7 +126,7 @@ k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int s = blockIdx.y;
   if (m >= MM) return;
-  const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
+  const int q = mode_at((int)(m / g.Mx), g.My), p = mode_at((int)(m % g.Mx), g.Mx);
   const Range rg = node_range(g, s);
   if (q >= g.my || p >= g.mx) {
     for (int n = rg.own_lo; n <= rg.own_hi; ++n) zhat[(long long)(n - 1) * MM + m] = (T)0;
@@ -178,7 +178,7 @@ k_modal_exact(Geom g, const double* __restrict__ rhat, const double* __restrict_
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int s = blockIdx.y;
   if (m >= MM) return;
-  const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
+  const int q = mode_at((int)(m / g.Mx), g.My), p = mode_at((int)(m % g.Mx), g.Mx);
   const Range rg = node_range(g, s);
   if (q >= g.my || p >= g.mx) {
     for (int n = rg.own_lo; n <= rg.own_hi; ++n) zhat[(long long)(n - 1) * MM + m] = 0.0;
@@ -223,7 +223,7 @@ k_modal_asm_add(Geom g, const double* __restrict__ ext, double* __restrict__ zha
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   const int s = blockIdx.y;
   if (m >= MM) return;
-  if ((int)(m / g.Mx) >= g.my || (int)(m % g.Mx) >= g.mx) return;
+  if (mode_at((int)(m / g.Mx), g.My) >= g.my || mode_at((int)(m % g.Mx), g.Mx) >= g.mx) return;
   const int E = g.delta * (1 + g.sym);
   if (s + 1 < g.nd)
     for (int i = 0; i < g.delta; ++i) {
@@ -244,7 +244,7 @@ k_modal_residual(Geom g, const double* __restrict__ zhat, const double* __restri
   const long long MM = g.padded();
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (m >= MM) return;
-  const int q = (int)(m / g.Mx), p = (int)(m % g.Mx);
+  const int q = mode_at((int)(m / g.Mx), g.My), p = mode_at((int)(m % g.Mx), g.Mx);
   if (q >= g.my || p >= g.mx) return;
   const double d = g.sigma + lamy[q] + lamx[p];
   double zp = 0.0, zc = zhat[m];
@@ -264,7 +264,7 @@ k_modal_prolong_add(Geom g, const double* __restrict__ c0, double* __restrict__ 
   const long long MM = g.padded();
   const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (m >= MM) return;
-  if ((int)(m / g.Mx) >= g.my || (int)(m % g.Mx) >= g.mx) return;
+  if (mode_at((int)(m / g.Mx), g.My) >= g.my || mode_at((int)(m % g.Mx), g.Mx) >= g.mx) return;
   for (int n = 1; n <= g.nt; ++n) zhat[(long long)(n - 1) * MM + m] += chat_at(g, c0, MM, m, n);
 }
 

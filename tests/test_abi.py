@@ -145,8 +145,11 @@ def test_launch_shape_table(lib):
     assert lib.kkt_tune_set(1, _lib.FP32, 512, 7, 4, 1) == 0
     assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d)) == 0
     assert (w.value, d.value) == (4, 1)
+    # wave counts must be even (each wave stays inside one half of the folded transform),
+    # extents multiples of 32, at most 8 tiles per wave
     for bad in [(2, 0, 128, 4, 8, 0), (0, 9, 128, 4, 8, 0), (0, 0, 100, 4, 4, 0), (0, 0, 128, 4, 3, 0),
-                (0, 0, 512, 4, 2, 0), (0, 0, 128, 0, 8, 0), (0, 0, 128, 4, 8, 2)]:
+                (0, 0, 128, 4, 1, 0), (0, 0, 16, 4, 2, 0), (0, 0, 512, 4, 2, 0), (0, 0, 128, 0, 8, 0),
+                (0, 0, 128, 4, 8, 2)]:
         assert lib.kkt_tune_set(*bad) == _lib.EINVAL, bad
 
 
