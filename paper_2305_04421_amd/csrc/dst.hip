@@ -352,8 +352,14 @@ __device__ inline const typename Eng::s_t* table(const void* S, int M, int inver
          (inverse ? (long long)Eng::kTableParts * M * (M >> 1) : 0);
 }
 
+// Three or four tiles per wave with the default ring: registers are capped so that two
+// 8-wave workgroups share a CU (one's loads and stores overlap the other's MFMAs), and the
+// right-hand-side operands are fetched after the first product instead of before it.
+template <int TPW, int PD>
+constexpr bool rows_two_per_cu() { return (TPW == 3 || TPW == 4) && PD == kPDDefault; }
+
 template <typename Eng, int TPW, int PD>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512, (rows_two_per_cu<TPW, PD>() ? 4 : 1))
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
@@ -372,39 +378,42 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   const int first = s * g.k + 1 - g.delta;
 
   // Right-hand-side operands of b at both points of every pair, fetched before GEMM1 so their
-  // latency hides behind it.
+  // latency hides behind it (after it where registers are capped).
   T pre[NPR][2];
-  if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
-    const int bnode = first + a.b_step;
-    const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
+  auto load_pre = [&]() {
+    if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
+      const int bnode = first + a.b_step;
+      const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
 #pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      const int e = threadIdx.x + i * nthr;
-      const int r = e / Hx, k = e - r * Hx;
-      const int row = rb * 16 + r;
-      T v1 = 0, v2 = 0;
-      if (row < g.my && k < Ax) {
-        const int c2 = mx - 1 - k;
-        if (a.b_mode == B_RPRIME_PLUS_Y) {
-          if (bnode >= 1) {
-            const double* src = a.rin + (long long)(bnode - 1) * g.nxy + (long long)row * mx;
-            v1 = (T)src[k];
-            v2 = (T)src[c2];
+      for (int i = 0; i < NPR; ++i) {
+        const int e = threadIdx.x + i * nthr;
+        const int r = e / Hx, k = e - r * Hx;
+        const int row = rb * 16 + r;
+        T v1 = 0, v2 = 0;
+        if (row < g.my && k < Ax) {
+          const int c2 = mx - 1 - k;
+          if (a.b_mode == B_RPRIME_PLUS_Y) {
+            if (bnode >= 1) {
+              const double* src = a.rin + (long long)(bnode - 1) * g.nxy + (long long)row * mx;
+              v1 = (T)src[k];
+              v2 = (T)src[c2];
+            }
+          } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
+            const T* src = a.ybuf_in + s * a.ybuf_stride + (long long)row * Mx;
+            v1 = src[k];
+            v2 = src[c2];
+          } else {
+            const double* src = a.rin + (long long)s * g.nxy + (long long)row * mx;
+            v1 = (T)(isc * src[k]);
+            v2 = (T)(isc * src[c2]);
           }
-        } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
-          const T* src = a.ybuf_in + s * a.ybuf_stride + (long long)row * Mx;
-          v1 = src[k];
-          v2 = src[c2];
-        } else {
-          const double* src = a.rin + (long long)s * g.nxy + (long long)row * mx;
-          v1 = (T)(isc * src[k]);
-          v2 = (T)(isc * src[c2]);
         }
+        pre[i][0] = v1;
+        pre[i][1] = v2;
       }
-      pre[i][0] = v1;
-      pre[i][1] = v2;
     }
-  }
+  };
+  if constexpr (!rows_two_per_cu<TPW, PD>()) load_pre();
 
   // ---- GEMM1: E | O = U(odd modes) F_odd^T | U(even modes) F_even^T, into the combine buffer
   if (a.g1_in) {
@@ -475,6 +484,7 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
     yv[i][1] = y2;
   }
   if (!form_b) return;
+  if constexpr (rows_two_per_cu<TPW, PD>()) load_pre();
   if constexpr (!Eng::kCombInPlace) __syncthreads();   // combine values read before the operand is written
 #pragma unroll
   for (int i = 0; i < NPR; ++i) {
