@@ -71,10 +71,11 @@ __device__ inline v4f mfma_bf(bf16x8 a, bf16x8 b, v4f c) {
 // Work split inside a workgroup: the M/16 column (or row) tiles of a 16-wide block are dealt
 // to nw waves (nw even), TPW tiles each, with nw * TPW == M/16 exactly (the padded extents
 // are chosen so that this holds).  Even waves take tiles of the odd-frequency half, odd waves
-// tiles of the even-frequency half, so every wave's tiles share one half of the operand.  The sine-matrix operand comes from L2 through a register ring that runs
-// ahead of the MFMAs, hiding the L2 latency; the LDS operand is read in place.  The ring is
-// PD k-steps deep: 4 by default, deeper (16 for one tile per wave, 8 for two to four) where
-// the autotuner measured it faster.
+// tiles of the even-frequency half, so every wave's tiles share one half of the operand.
+// The table operand comes from L2 through a register ring that runs ahead of the MFMAs,
+// hiding the L2 latency; the LDS operand is read in place.  The ring is PD k-steps deep: 4 by
+// default; deeper rings (16 for one tile per wave, 8 for two to four) can be selected with
+// kkt_tune_set.
 constexpr int kPDDefault = 4;
 template <int TPW>
 constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
@@ -957,14 +958,14 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     // candidates: the default shape first, then every other valid shape
     Shape cand[32];
     int nc = 0;
+    // (the deep rings are not candidates: with the folded products' half-length k-loops they
+    // measured slower than the default ring at every extent; tune_set can still select them)
     cand[nc++] = Shape{waves_for(M), 0};
     for (int nw : {2, 4, 8, t}) {
       if (nw < 2 || nw > 8 || (nw & 1) || t % nw != 0 || t / nw > 8) continue;
-      for (int deep = 0; deep <= (t / nw <= 4 ? 1 : 0); ++deep) {
-        bool seen = false;
-        for (int i = 0; i < nc; ++i) seen = seen || (cand[i].nw == nw && cand[i].deep == deep);
-        if (!seen && nc < 32) cand[nc++] = Shape{nw, deep};
-      }
+      bool seen = false;
+      for (int i = 0; i < nc; ++i) seen = seen || cand[i].nw == nw;
+      if (!seen && nc < 32) cand[nc++] = Shape{nw, 0};
     }
     // rounds of 4 launches per candidate, candidates interleaved; a candidate's time is its
     // fastest round.  The default shape is kept unless another is at least 5% faster.
