@@ -42,7 +42,8 @@ k_restrict(Geom g, const double* __restrict__ rw, const double* __restrict__ dsc
 }
 
 // Band storage of the Gram matrices: G[i*(hb+1) + b] = G(i, i-b), b = 0..hb.
-// Factor: fac[(i*(hb+1) + b) * nmodes + mode] = L(i, i-b) (lower Cholesky factor).
+// Factor: fac[(i*(hb+1) + b) * nmodes + mode] = L(i, i-b) (lower Cholesky factor) for b >= 1,
+// and 1 / L(i, i) for b = 0 (the solves multiply by it).
 __global__ void __launch_bounds__(kBlock)
 k_coarse_factor(Geom g, const double* __restrict__ G2, const double* __restrict__ G0,
                 const double* __restrict__ G1, const double* __restrict__ lamx,
@@ -67,26 +68,28 @@ k_coarse_factor(Geom g, const double* __restrict__ G2, const double* __restrict_
         a -= L(i, m) * L(j, m);
       }
       if (j < i) {
-        L(i, j) = a / L(j, j);
+        L(i, j) = a * L(j, j);   // L(j, j) holds the reciprocal diagonal
       } else {
         if (!(a > 0.0)) {
           *info = 1;
           a = 1.0;
         }
-        L(i, i) = sqrt(a);
+        L(i, i) = 1.0 / sqrt(a);
       }
     }
   }
 }
 
-// In-place solve of every mode's band system on padded sine-mode slices xhat[slot][q][p].
-// The substitutions keep the last hb solved values in registers, so the dependency chain
-// runs through registers rather than through memory; the loads of the right-hand side and
-// of the factor do not depend on the chain.
+// In-place solve of every mode's band system on padded sine-mode slices xhat[slot][q][p]:
+// forward L y = r, then backward L^T c = y column by column (once c_i is known, its
+// contributions L(i, i-b) c_i leave the pending values of rows i-1 .. i-hb), so both passes
+// need only row i of the factor at step i.  Rows and right-hand sides come through a register
+// ring kRing steps ahead of the chain, which runs through registers; the loads do not depend
+// on it.
 template <int NB>
 __global__ void __launch_bounds__(64)
 k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat) {
-  constexpr int hb = 2 * NB - 1, w = hb + 1;
+  constexpr int hb = 2 * NB - 1, w = hb + 1, kRing = 8;
   const int mode = blockIdx.x * 64 + threadIdx.x;
   const int nmodes = g.nxy;
   if (mode >= nmodes) return;
@@ -95,64 +98,69 @@ k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat
   const double* Lm = fac + mode;
   const long long ld = nmodes;
   const int nc = g.nc;
-  // Row i of the band factor: L(i,i) and L(i,i-b), b = 1..hb, at Lm[(i*w + b)*ld].  The loads of
-  // row i+1 (and of the next right-hand side) are issued before row i is used, so their
-  // latency overlaps the substitution chain.
+  // row i of the factor: 1/L(i,i), then L(i,i-b), b = 1..hb, at Lm[(i*w + b)*ld]
   auto load_row = [&](int i, double (&row)[w]) {
 #pragma unroll
     for (int b = 0; b < w; ++b) row[b] = (i >= 0 && i < nc) ? Lm[((long long)i * w + b) * ld] : 0.0;
   };
-  // forward: L y = r;  win[b] = y_{i-1-b}
+  auto load_x = [&](int i) { return (i >= 0 && i < nc) ? x[(long long)i * MM] : 0.0; };
+  double ring[kRing][w], rv[kRing];
+
+  // forward: y_i = (r_i - sum_b L(i,i-b) y_{i-b}) / L(i,i);  win[b] = y_{i-1-b}
   double win[hb];
 #pragma unroll
   for (int b = 0; b < hb; ++b) win[b] = 0.0;
-  double cur[w], nxt[w];
-  load_row(0, cur);
-  double rcur = x[0], rnxt = 0.0;
-  for (int i = 0; i < nc; ++i) {
-    load_row(i + 1, nxt);
-    if (i + 1 < nc) rnxt = x[(i + 1) * MM];
-    double a = rcur;
 #pragma unroll
-    for (int b = 1; b <= hb; ++b)
-      if (i - b >= 0) a -= cur[b] * win[b - 1];
-    const double y = a / cur[0];
-    x[i * MM] = y;
-#pragma unroll
-    for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
-    win[0] = y;
-#pragma unroll
-    for (int b = 0; b < w; ++b) cur[b] = nxt[b];
-    rcur = rnxt;
+  for (int d = 0; d < kRing; ++d) {
+    load_row(d, ring[d]);
+    rv[d] = load_x(d);
   }
-  // backward: L^T c = y;  win[b] = c_{i+1+b}.  Needs L(i+b, i) = row i+b, entry b, and
-  // L(i,i); the column of the factor below the diagonal is kept in a rolling window.
+  for (int i0 = 0; i0 < nc; i0 += kRing) {
 #pragma unroll
-  for (int b = 0; b < hb; ++b) win[b] = 0.0;
-  double below[hb + 1][w];   // rows i, i+1, .., i+hb of the factor
+    for (int d = 0; d < kRing; ++d) {
+      const int i = i0 + d;
+      if (i >= nc) break;
+      double a = rv[d];
 #pragma unroll
-  for (int d = 0; d <= hb; ++d) load_row(nc - 1 + d, below[d]);
-  double ycur = x[(nc - 1) * MM], ynxt = 0.0;
-  for (int i = nc - 1; i >= 0; --i) {
-    double prev[w];
-    load_row(i - 1, prev);
-    if (i - 1 >= 0) ynxt = x[(i - 1) * MM];
-    double a = ycur;
+      for (int b = 1; b <= hb; ++b)
+        if (i - b >= 0) a -= ring[d][b] * win[b - 1];   // entries before row 0 are not stored
+      const double y = a * ring[d][0];
+      x[(long long)i * MM] = y;
 #pragma unroll
-    for (int b = 1; b <= hb; ++b)
-      if (i + b < nc) a -= below[b][b] * win[b - 1];
-    const double c = a / below[0][0];
-    x[i * MM] = c;
+      for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
+      win[0] = y;
+      load_row(i + kRing, ring[d]);
+      rv[d] = load_x(i + kRing);
+    }
+  }
+
+  // backward: c_i = pend_i / L(i,i), then pend_{i-b} -= L(i,i-b) c_i.  cur = pend_i,
+  // acc[b] = pend_{i-1-b}; the value entering the window at step i is y_{i-1-hb}.
+  double cur = win[0], acc[hb];
 #pragma unroll
-    for (int b = hb - 1; b > 0; --b) win[b] = win[b - 1];
-    win[0] = c;
+  for (int b = 0; b < hb; ++b) acc[b] = b + 1 < hb ? win[b + 1] : load_x(nc - 1 - hb);
 #pragma unroll
-    for (int d = hb; d > 0; --d)
+  for (int d = 0; d < kRing; ++d) {
+    load_row(nc - 1 - d, ring[d]);
+    rv[d] = load_x(nc - 2 - hb - d);
+  }
+  for (int i0 = nc - 1; i0 >= 0; i0 -= kRing) {
 #pragma unroll
-      for (int b = 0; b < w; ++b) below[d][b] = below[d - 1][b];
+    for (int d = 0; d < kRing; ++d) {
+      const int i = i0 - d;
+      if (i < 0) break;
+      const double c = cur * ring[d][0];
+      x[(long long)i * MM] = c;
 #pragma unroll
-    for (int b = 0; b < w; ++b) below[0][b] = prev[b];
-    ycur = ynxt;
+      for (int b = 1; b <= hb; ++b)
+        if (i - b >= 0) acc[b - 1] -= ring[d][b] * c;
+      cur = acc[0];
+#pragma unroll
+      for (int b = 0; b + 1 < hb; ++b) acc[b] = acc[b + 1];
+      acc[hb - 1] = rv[d];
+      load_row(i - kRing, ring[d]);
+      rv[d] = load_x(i - 1 - hb - kRing);
+    }
   }
 }
 
