@@ -128,7 +128,7 @@ def main():
         del u0, ut
     unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
 
-    def run_path(precision, steps, warmup, profile, sweep="step", must_converge=True):
+    def run_path(precision, steps, warmup, profile, sweep="step", must_converge=True, keep_x=False):
         solvers = [KKTSolver(p, precision, sweep=sweep) for _, p, _, _ in probs]
         fs = [S.rhs(u0, ut) for S, (_, _, u0, ut) in zip(solvers, probs)]
         xs = [torch.zeros_like(f) for f in fs]
@@ -174,10 +174,12 @@ def main():
                 S.profile(False)
         for S in solvers:
             S.close()
-        return dt, stats, prof
+        return dt, stats, prof, (xs if keep_x else None)
 
-    # float64 path
-    dt64, st64, prof64 = run_path("fp64", args.steps, args.warmup, profile=True)
+    # float64 path; its solutions (host copies) are the reference of the other paths' errors
+    dt64, st64, prof64, xs64 = run_path("fp64", args.steps, args.warmup, profile=True, keep_x=True)
+    x64 = [x.cpu() for x in xs64]
+    del xs64
     value64 = args.steps * sum(unknowns) / dt64
     result = {
         "metric": METRIC, "value": value64, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
@@ -191,6 +193,8 @@ def main():
         "reorthogonalised_steps": {name: st["reorth"] for (name, _, _, _), st in zip(probs, st64)},
         "batched": not args.sequential,
         "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st64)},
+        # ||f_b - (K x)_b|| / ||f_b|| per block (u, z, w; 0 where f_b = 0)
+        "relres_block": {name: st["relres_block"] for (name, _, _, _), st in zip(probs, st64)},
     }
 
     # roofline of the dominant kernel class (or the one asked for)
@@ -226,16 +230,30 @@ def main():
     roof["timed_on"] = "one extra step, its solves run one after another, HIP events around every launch"
     result["roofline"] = roof
 
+    def err_vs_fp64(xs):
+        # relative 2-norm distance of each solution from the float64 per-step path's
+        out = {}
+        for (name, _, _, _), x, ref in zip(probs, xs, x64):
+            r = ref.to(dev)
+            out[name] = float((x - r).norm() / r.norm())
+            del r
+        return out
+
     def summary(prec, sweep):
-        dt, st, _ = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep, must_converge=False)
+        dt, st, _, xs = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep,
+                                 must_converge=False, keep_x=True)
+        err = err_vs_fp64(xs)
+        del xs
         failed = [name for (name, _, _, _), x in zip(probs, st) if x["status"] != 0]
         if failed:
             return {"value": None, "not_converged": failed, "ms_per_step": 1e3 * dt / args.steps,
-                    "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)}}
+                    "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
+                    "err_vs_fp64": err}
         v = args.steps * sum(unknowns) / dt
         return {"value": v, "ms_per_step": 1e3 * dt / args.steps, "ratio_vs_fp64": v / value64,
                 "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
-                "relres_true": {name: x["relres_true"] for (name, _, _, _), x in zip(probs, st)}}
+                "relres_true": {name: x["relres_true"] for (name, _, _, _), x in zip(probs, st)},
+                "err_vs_fp64": err}
 
     if not args.no_mixed:
         # reduced-precision sweeps and sine-transform GEMMs; FGMRES, matvec and coarse level
