@@ -72,7 +72,9 @@ DESCRIPTIONS = {
 # kernel class, as recorded in profiles/arnoldi_<workload>_fp64_hbm_counters.md for the
 # current kernels.  A class whose kernels changed since the counters were taken, or a
 # workload without counters, is absent (traffic null).
-TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.81e6}}
+TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.79e6},
+           "grid256": {"arnoldi": 8900.26e6, "matvec": 3703.47e6},
+           "grid512": {"arnoldi": 34507.49e6, "matvec": 31438.59e6}}
 
 
 def parse():
@@ -177,8 +179,9 @@ def main():
         return dt, stats, prof, (xs if keep_x else None)
 
     # float64 path; its solutions (host copies) are the reference of the other paths' errors
-    dt64, st64, prof64, xs64 = run_path("fp64", args.steps, args.warmup, profile=True, keep_x=True)
-    x64 = [x.cpu() for x in xs64]
+    others = not (args.no_mixed and args.no_hoisted)
+    dt64, st64, prof64, xs64 = run_path("fp64", args.steps, args.warmup, profile=True, keep_x=others)
+    x64 = [x.cpu() for x in xs64] if others else None
     del xs64
     value64 = args.steps * sum(unknowns) / dt64
     result = {
