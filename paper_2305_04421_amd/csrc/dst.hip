@@ -331,7 +331,7 @@ struct RowArgs {
   const T* g1_in;            // padded slices (nullptr: y = 0)
   long long g1_stride;
   double g1_scale;
-  T* ystore;                 // padded; nullptr: no store
+  T* ystore;                 // padded layout, interior points written; nullptr: no store
   long long ystore_stride;
   int out_mode;
   double* out64;             // OUT_OWNED: z_w field (nt slices); OUT_PLAIN: nslices slices
