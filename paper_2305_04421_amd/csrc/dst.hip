@@ -110,20 +110,24 @@ struct EngPlain {
     (void)M;
     reinterpret_cast<T*>(lds)[k * 17 + c] = v;
   }
+  // Table loads: a wave-uniform base (block, k-step) plus a 32-bit per-lane offset per tile.
   template <int TPW, int kPD>
   static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
-    const T* Sp = Q + (long long)blk * H * H + (long long)lk * H + lt0 * 16 + li;
-    const long long tstride = (long long)lts * 16;
+    const T* Qb = Q + (long long)blk * H * H;
+    int voff[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
     const int nks = H >> 2;
     T bq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
       if (p < nks) {
+        const T* Qk = Qb + (long long)(4 * p) * H;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * p) * H + t * tstride];
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
       }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
@@ -135,8 +139,9 @@ struct EngPlain {
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
         const int kn = ks + kPD;
         if (kn < nks) {
+          const T* Qk = Qb + (long long)(4 * kn) * H;
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) bq[p][t] = Sp[(long long)(4 * kn) * H + t * tstride];
+          for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
         }
       }
     }
@@ -146,16 +151,18 @@ struct EngPlain {
                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
-    // A(row = li, k = lk) of local tile lt is Q[blk][k][lt*16 + li]
-    const T* Sp = Q + (long long)blk * H * H + (long long)lk * H + lt0 * 16 + li;
-    const long long tstride = (long long)lts * 16;
+    const T* Qb = Q + (long long)blk * H * H;
+    int voff[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
     const int nks = H >> 2;
     T aq[kPD][TPW];
 #pragma unroll
     for (int p = 0; p < kPD; ++p)
       if (p < nks) {
+        const T* Qk = Qb + (long long)(4 * p) * H;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * p) * H + t * tstride];
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
       }
     for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
 #pragma unroll
@@ -167,8 +174,9 @@ struct EngPlain {
         for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
         const int kn = ks + kPD;
         if (kn < nks) {
+          const T* Qk = Qb + (long long)(4 * kn) * H;
 #pragma unroll
-          for (int t = 0; t < TPW; ++t) aq[p][t] = Sp[(long long)(4 * kn) * H + t * tstride];
+          for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
         }
       }
     }
@@ -237,13 +245,13 @@ struct EngBF {
     return mfma_bf(a[0], b[0], acc);
   }
   static constexpr int ring(int TPW) { return TPW * NP <= 8 ? 2 : 1; }
-  // fragment of local tile lt at k-step ks: Q_p[blk][lt*16 + li][32ks + 8lk .. +8]
+  // fragment of local tile lt at k-step ks: Q_p[blk][lt*16 + li][32ks + 8lk .. +8], as a
+  // wave-uniform base (part, block, k-step) plus a 32-bit per-lane offset
   static __device__ bf16x8 qload(const __bf16* __restrict__ Q, int M, int blk, int lt, int ks,
                                  int p, int li, int lk) {
     const int H = M >> 1;
-    const long long row = (long long)lt * 16 + li;
-    return *reinterpret_cast<const bf16x8*>(Q + (long long)p * M * H + (long long)blk * H * H +
-                                            row * H + 32 * ks + 8 * lk);
+    const __bf16* base = Q + (long long)p * M * H + (long long)blk * H * H + 32 * ks;
+    return *reinterpret_cast<const bf16x8*>(base + ((lt * 16 + li) * H + 8 * lk));
   }
   template <int TPW, int PD_unused>
   static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ Q, int M,
@@ -368,7 +376,7 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   const int Mx = g.Mx, Hx = Mx >> 1, mx = g.mx, Ax = (mx + 1) / 2, ldc = Mx + 1;
   const int rb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
   T* comb = reinterpret_cast<T*>(smem_raw);
@@ -551,7 +559,7 @@ k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   const int Mx = g.Mx, My = g.My, Hy = My >> 1, my = g.my, Ay = (my + 1) / 2;
   const int cb = blockIdx.x, s = blockIdx.y;
   const int nthr = blockDim.x, nw = nthr >> 6;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
   T* comb = reinterpret_cast<T*>(smem_raw);
@@ -582,29 +590,29 @@ k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   __syncthreads();
 
   acc_t acc[TPW];
-  const int npass = 1 + a.two;
-  for (int pass = 0; pass < npass; ++pass) {
+  auto product = [&](int inverse) {
 #pragma unroll
     for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    const int inverse = !(pass == 0 && a.fold);
     Eng::template gemm_left<TPW, PD>(table<Eng>(a.Sy, My, inverse), smem_raw, My, blk, lt0, lts, li, lk, acc);
-    if (pass == 0 && a.invlam) {
+  };
+  product(!a.fold);
+  if (a.invlam) {
+    const T* il = a.invlam + (long long)(blk * Hy + lt0 * 16) * Mx + cb * 16;
 #pragma unroll
-      for (int t = 0; t < TPW; ++t)
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          acc[t][r] *= a.invlam[(long long)(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * Mx +
-                                cb * 16 + li];
-    }
-    if (pass + 1 < npass) {
-      __syncthreads();
+      for (int r = 0; r < 4; ++r)
+        acc[t][r] *= il[(t * lts * 16 + Eng::acc_row(lk, r)) * Mx + li];
+  }
+  if (a.two) {
+    __syncthreads();
 #pragma unroll
-      for (int t = 0; t < TPW; ++t)
+    for (int t = 0; t < TPW; ++t)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          Eng::put_b(smem_raw, My, blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
-      __syncthreads();
-    }
+      for (int r = 0; r < 4; ++r)
+        Eng::put_b(smem_raw, My, blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
+    __syncthreads();
+    product(1);
   }
   T* dst = a.out + s * a.out_stride + cb * 16;
   if (a.fold && !a.two) {   // forward only: y-mode rows
