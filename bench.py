@@ -72,9 +72,9 @@ DESCRIPTIONS = {
 # kernel class, as recorded in profiles/arnoldi_<workload>_fp64_hbm_counters.md for the
 # current kernels.  A class whose kernels changed since the counters were taken, or a
 # workload without counters, is absent (traffic null).
-TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.79e6},
-           "grid256": {"arnoldi": 8900.26e6, "matvec": 3703.47e6},
-           "grid512": {"arnoldi": 34507.49e6, "matvec": 31438.59e6}}
+TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.83e6},
+           "grid256": {"arnoldi": 8900.26e6, "matvec": 3687.70e6},
+           "grid512": {"arnoldi": 34507.54e6, "matvec": 31325.91e6}}
 
 
 def parse():
