@@ -8,6 +8,10 @@ grid512 (511^2 x 2048, 128 subdomains, 1.6e9 unknowns): outputs the oracle can c
 a time.  Rows of K x and f at sampled time nodes (a row of node n involves nodes n-1..n+1
 only, so the oracle evaluates it on a three-node window); the one-level sweeps of sampled
 subdomains; and the FGMRES(12) solution's residual at sampled time nodes.
+
+grid128 pair (127^2 x 256, omega 1e-2 and 1e-4) and the uneven batch (64 problems): solved
+together by kkt_solve_batched as the bench solves them; whole-field parity of the grid128
+operators, and every solution's residual recomputed by the oracle.
 """
 
 import numpy as np
@@ -73,6 +77,68 @@ def test_grid256_solve_residual_by_oracle():
     # the library's own true residual agrees with the oracle's (a difference of nearly equal
     # quantities, so only to the relative rounding of ||f|| / ||f - Kx||)
     assert abs(res - st["relres_true"]) <= 1e-4 * res
+
+
+# ---- grid128 pair and the uneven batch, solved as one batch -----------------------------------
+
+def _batched_residuals(cases, restart):
+    """Solve every (params, recipe) case in one kkt_solve_batched call to 1e-8; return the
+    oracle's relative residual of each solution and the library's stats."""
+    from paper_2305_04421_amd import KKTSolver, solve_batched
+    solvers, fs, fh = [], [], []
+    try:
+        for params, recipe in cases:
+            p = Problem(**params).validate()
+            u0, ut = wl.data(params, recipe)
+            f = op.rhs(p, u0, ut)
+            S = KKTSolver(params)
+            solvers.append(S)
+            fs.append(S.rhs(dev(u0), dev(ut)))
+            fh.append((p, f))
+        xs, sts = solve_batched(solvers, fs, restart=restart, maxit=600, rtol=1e-8)
+        out = []
+        for (p, f), x, st in zip(fh, xs, sts):
+            xh = x.cpu().numpy().reshape((3,) + p.field_shape)
+            out.append((np.linalg.norm(f - op.apply_K(p, xh)) / np.linalg.norm(f), st))
+        return out
+    finally:
+        for S in solvers:
+            S.close()
+
+
+def test_grid128_pair_operators_whole_field():
+    from paper_2305_04421_amd import KKTSolver
+    for name in ("grid128", "grid128_w4"):
+        params, recipe = wl.config(name)
+        p = Problem(**params).validate()
+        shape = (3,) + p.field_shape
+        u0, ut = wl.data(params, recipe)
+        r = wl.random_field(shape, 12)
+        with KKTSolver(params) as S:
+            fd = S.rhs(dev(u0), dev(ut)).cpu().numpy().reshape(shape)
+            y = S.apply(dev(r)).cpu().numpy().reshape(shape)
+            z = S.precond(dev(r)).cpu().numpy().reshape(shape)
+        assert relerr(fd, op.rhs(p, u0, ut)) <= 1e-13, name
+        assert relerr(y, op.apply_K(p, r)) <= 1e-13, name
+        assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-11, name
+
+
+def test_grid128_pair_batched_solve_residuals():
+    cases = [wl.config(name) for name in ("grid128", "grid128_w4")]
+    for res, st in _batched_residuals(cases, restart=30):
+        assert st["status"] == 0, st
+        assert res <= 1e-8
+        assert abs(res - st["relres_true"]) <= 1e-4 * res
+
+
+def test_uneven_batch_solve_residuals():
+    cases = list(wl.batch_uneven(64, seed=4))
+    results = _batched_residuals(cases, restart=12)
+    assert len(results) == 64
+    for res, st in results:
+        assert st["status"] == 0, st
+        assert res <= 1e-8
+        assert abs(res - st["relres_true"]) <= 1e-4 * res
 
 
 # ---- grid512: sampled outputs ------------------------------------------------------------
