@@ -107,7 +107,8 @@ struct kktdd_handle {
   int elem = 8;                       // bytes per element of the sweep work buffers
   std::vector<void*> allocations;
 
-  // tables
+  // tables: per extent the forward then inverse half-transform blocks (see dst.hip), and
+  // the inverse eigenvalues in the folded mode order
   double *Sx64 = nullptr, *Sy64 = nullptr, *invlam64 = nullptr;
   float *Sx32 = nullptr, *Sy32 = nullptr, *invlam32 = nullptr;
   double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
@@ -132,9 +133,9 @@ struct kktdd_handle {
   double* host_hcol = nullptr;                 // pinned, KrylovSmall(R).host doubles
   Prof prof;
 
-  uint16_t *SxBF = nullptr, *SyBF = nullptr;  // bfloat16 parts (3 per matrix) of S_x, S_y
+  uint16_t *SxBF = nullptr, *SyBF = nullptr;  // three bfloat16 parts of each table (transposed blocks)
 
-  // sine-matrix operand and eigenvalue table of the handle's GEMM engine
+  // half-transform tables and eigenvalue table of the handle's GEMM engine
   const void* Sx() const {
     switch (prob.precision) {
       case KKTDD_FP64: return Sx64;

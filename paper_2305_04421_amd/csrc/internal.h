@@ -118,7 +118,8 @@ int launch_coarse_dst(const Geom& g, const double* Sx, const double* Sy, const d
 int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const double* chat,
                        double* c0, double* tmp, double norm, hipStream_t s);
 
-// Batched 2-D sine transforms of nslices slices in the handle's precision:
+// Batched 2-D sine transforms of nslices slices in the handle's precision (folded products;
+// padded mode space in the order of mode_pos):
 //   forward  out = S_y (scale*in) S_x   (in: unpadded float64 slices; out, tmp: padded)
 //   inverse  out = norm * S_y in S_x    (in, tmp: padded; out: unpadded float64 slices),
 //            plus the coarse part Z c0 when c0 != nullptr (the slices are time-nodes 1..nt)
