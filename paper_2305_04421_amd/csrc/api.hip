@@ -30,6 +30,7 @@ bool arnoldi_dcgs2() {
   return v;
 }
 constexpr int kRedBlocks = 1024;   // most blocks of a two-stage reduction
+constexpr long kBatchStaggerUs = 300;   // start offset of the odd members of a batch
 constexpr int kFieldSums = 3;      // per-block partial sums of a field reduction
 constexpr int kMaxCgsRestart = 31; // the CGS passes keep one accumulator per basis vector
 constexpr double kReorthEta = 0.70710678118654752;  // 1/sqrt(2)
@@ -1177,8 +1178,14 @@ int kkt_solve_batched(int32_t n, kktdd_handle* const* hs, const double* const* f
     (void)hipGetDevice(&device);
     std::vector<std::thread> pool;
     pool.reserve(n);
+    // Odd members start a little later, so that one problem's bandwidth-bound Arnoldi passes
+    // tend to meet another's latency-bound sweeps rather than its own Arnoldi passes
+    // (KKTDD_BATCH_STAGGER_US overrides; 0 starts every member at once).
+    const char* stg = std::getenv("KKTDD_BATCH_STAGGER_US");
+    const long stagger_us = stg ? std::atol(stg) : kBatchStaggerUs;
     for (int i = 0; i < n; ++i) {
       pool.emplace_back([&, i]() {
+        if (stagger_us > 0 && (i & 1)) std::this_thread::sleep_for(std::chrono::microseconds(stagger_us));
         (void)hipSetDevice(device);
         hs[i]->stream = priv[i];
         codes[i] = fgmres_solve(hs[i], f[i], x[i], restart, maxit, rtol, stats ? stats + i : nullptr);
