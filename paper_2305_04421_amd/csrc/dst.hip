@@ -353,7 +353,27 @@ struct RowArgs {
   long long ybuf_stride;
   T* g2_out;                 // padded
   long long g2_stride;
+  int nsl;                   // set by the launcher: slice count of the slice-per-XCD grid, or 0
 };
+
+// Workgroup placement of the row and column kernels.  Workgroups are dealt to the XCDs
+// round-robin by linear id.  The two-dimensional grid (tile, slice) spreads every slice over
+// all XCDs.  The slice-per-XCD grid is one-dimensional, kXcds * ceil(nslices / kXcds) * ntile
+// workgroups: id = x + kXcds * q runs tile q % ntile of slice x + kXcds * (q / ntile) on XCD
+// x, so the slice one launch writes is read by the next launch on the same XCD (from its L2
+// while the slices fit there).  Ids past the last slice exit at once.
+constexpr int kXcds = 8;
+__device__ inline bool tile_and_slice(int ntile, int nsl, int& tile, int& slice) {
+  if (nsl == 0) {
+    tile = blockIdx.x;
+    slice = blockIdx.y;
+    return true;
+  }
+  const int q = blockIdx.x / kXcds, c = q / ntile;
+  slice = blockIdx.x % kXcds + kXcds * c;
+  tile = q - c * ntile;
+  return slice < nsl;
+}
 
 template <typename Eng>
 __device__ inline const typename Eng::s_t* table(const void* S, int M, int inverse) {
@@ -374,7 +394,8 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using acc_t = typename Eng::acc_t;
   extern __shared__ unsigned char smem_raw[];
   const int Mx = g.Mx, Hx = Mx >> 1, mx = g.mx, Ax = (mx + 1) / 2, ldc = Mx + 1;
-  const int rb = blockIdx.x, s = blockIdx.y;
+  int rb, s;
+  if (!tile_and_slice((g.my + 15) / 16, a.nsl, rb, s)) return;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -548,6 +569,7 @@ struct ColArgs {
   int two;             // chain the inverse product (needs fold)
   T* out;
   long long out_stride;
+  int nsl = 0;         // set by the launcher: slice count of the slice-per-XCD grid, or 0
 };
 
 template <typename Eng, int TPW, int PD>
@@ -557,7 +579,8 @@ k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using acc_t = typename Eng::acc_t;
   extern __shared__ unsigned char smem_raw[];
   const int Mx = g.Mx, My = g.My, Hy = My >> 1, my = g.my, Ay = (my + 1) / 2;
-  const int cb = blockIdx.x, s = blockIdx.y;
+  int cb, s;
+  if (!tile_and_slice(g.Mx / 16, a.nsl, cb, s)) return;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
@@ -720,6 +743,19 @@ int allow_lds(F* kernel, size_t lds) {
   return 0;
 }
 
+// The slice-per-XCD grid pays off while the slices of a launch fit the XCDs' L2 caches
+// (measured at padded 128 x 128 x 16 slices in float64: a row + column step pair 17.7 ->
+// 16.4 us; at 256 x 256 x 64 slices it was 0.5% slower).  KKTDD_XCD_MAP=0/1 forces it.
+inline bool slice_per_xcd(const Geom& g, int nslices, size_t elem) {
+  const char* v = std::getenv("KKTDD_XCD_MAP");
+  if (v && *v) return std::atoi(v) != 0;
+  return (double)nslices * g.Mx * g.My * (double)elem <= 8.0 * 1024 * 1024;
+}
+
+inline dim3 sweep_grid(int ntile, int nslices, int nsl) {
+  return nsl ? dim3(kXcds * ((nslices + kXcds - 1) / kXcds) * ntile) : dim3(ntile, nslices);
+}
+
 // Flops of the folded products: a 1-D transform of extent m costs 2*(A^2 + B^2) per vector,
 // A = ceil(m/2), B = floor(m/2) (about half of the unfolded 2*m^2).
 inline double folded_flops(int m) {
@@ -734,8 +770,11 @@ int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, i
   if (int e = allow_lds(k_rows<Eng, TPW, PD>, lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
+  RowArgs<typename Eng::data_t> la = a;
+  la.nsl = slice_per_xcd(g, nslices, sizeof(typename Eng::data_t)) ? nslices : 0;
   // row blocks past the interior would only write padding rows, which nothing reads
-  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), dim3((g.my + 15) / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), sweep_grid((g.my + 15) / 16, nslices, la.nsl),
+                     dim3(64 * nw), lds, s, g, la);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, ngemm * nslices * (double)g.my * folded_flops(g.mx));
   return 0;
@@ -747,7 +786,10 @@ int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, i
   const size_t lds = Eng::cols_lds_total(g.My);
   if (int e = allow_lds(k_cols<Eng, TPW, PD>, lds)) return e;
   prof_begin(kclass, s);
-  hipLaunchKernelGGL((k_cols<Eng, TPW, PD>), dim3(g.Mx / 16, nslices), dim3(64 * nw), lds, s, g, a);
+  ColArgs<typename Eng::data_t> la = a;
+  la.nsl = slice_per_xcd(g, nslices, sizeof(typename Eng::data_t)) ? nslices : 0;
+  hipLaunchKernelGGL((k_cols<Eng, TPW, PD>), sweep_grid(g.Mx / 16, nslices, la.nsl), dim3(64 * nw),
+                     lds, s, g, la);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, (1 + a.two) * nslices * (double)g.mx * folded_flops(g.my));
   return 0;

@@ -163,6 +163,29 @@ def test_launch_shapes_give_identical_results(precision, sweep):
                 lib.kkt_tune_set(kind, prec, M, ns, w, d)
 
 
+@pytest.mark.parametrize("case,sweep", [("full_tiles_overlap_k", "step"), ("full_tiles_overlap_k", "modal"),
+                                        ("tiny32", "step")])
+def test_workgroup_placement_gives_identical_results(case, sweep, monkeypatch):
+    """Both workgroup placements of the transform kernels (slices spread over the XCDs, or one
+    XCD per slice with a one-dimensional grid whose surplus workgroups exit) compute every
+    tile the same way: the preconditioner is bitwise equal, also for slice counts that are not
+    multiples of eight."""
+    params = CASES[case]
+    p = Problem(**params).validate()
+    r = wl.random_field((3,) + p.field_shape, 23)
+    rd = dev(r)
+    with solver(params, sweep=sweep) as S:
+        out = {}
+        for mode in ("0", "1"):
+            monkeypatch.setenv("KKTDD_XCD_MAP", mode)
+            out[mode] = S.precond(rd).clone()
+        monkeypatch.delenv("KKTDD_XCD_MAP")
+        out["auto"] = S.precond(rd).clone()
+    assert torch.equal(out["0"], out["1"])
+    assert torch.equal(out["0"], out["auto"])
+    assert relerr(host(out["1"], r.shape), pc.apply_Pinv(p, r)) <= 1e-11
+
+
 def test_precond_is_deterministic():
     params = CASES["tiny32"]
     p = Problem(**params).validate()
