@@ -153,7 +153,9 @@ int kkt_precision(const kktdd_handle* h);
  * measures the candidates on its own extents and keeps the fastest for the process (disable
  * with KKTDD_AUTOTUNE=0; KKTDD_TUNE_CACHE=<file> keeps them across processes, one JSON object
  * per line).  Every shape performs the same operations in the same order, so results do not
- * depend on it.  Host-only; set returns KKTDD_EINVAL for an invalid shape. */
+ * depend on it; neither do they on the workgroup placement (one XCD per slice when a launch's
+ * slices take at most 8 MiB, else slices spread over the XCDs; KKTDD_XCD_MAP=0|1 forces it).
+ * Host-only; set returns KKTDD_EINVAL for an invalid shape. */
 int kkt_tune_set(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t waves,
                  int32_t deep);
 int kkt_tune_get(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t* waves,
