@@ -163,14 +163,18 @@ def test_launch_shapes_give_identical_results(precision, sweep):
                 lib.kkt_tune_set(kind, prec, M, ns, w, d)
 
 
+PLACEMENT_CASES = dict(CASES, eleven_subdomains=wl.problem(nx=40, ny=33, nt=22, Lx=1.0, Ly=0.8, nu=0.4,
+                                                           omega=1e-3, n_sub=11, overlap=1, coarse=2))
+
+
 @pytest.mark.parametrize("case,sweep", [("full_tiles_overlap_k", "step"), ("full_tiles_overlap_k", "modal"),
-                                        ("tiny32", "step")])
+                                        ("tiny32", "step"), ("eleven_subdomains", "step")])
 def test_workgroup_placement_gives_identical_results(case, sweep, monkeypatch):
     """Both workgroup placements of the transform kernels (slices spread over the XCDs, or one
     XCD per slice with a one-dimensional grid whose surplus workgroups exit) compute every
     tile the same way: the preconditioner is bitwise equal, also for slice counts that are not
     multiples of eight."""
-    params = CASES[case]
+    params = PLACEMENT_CASES[case]
     p = Problem(**params).validate()
     r = wl.random_field((3,) + p.field_shape, 23)
     rd = dev(r)
