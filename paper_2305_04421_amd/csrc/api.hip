@@ -389,12 +389,31 @@ int build_tables(kktdd_handle* H) {
     }
     return Q;
   };
+  // The plain engines read each H x H block with k-steps (groups of four rows) interleaved in
+  // pairs: row 4ks + lk, column c goes to ((ks/2 * 4 + lk) H + c) * 2 + ks % 2.
+  auto pair_rows = [](std::vector<double>& Q, int M) {
+    const int H = M / 2;
+    std::vector<double> out(Q.size());
+    for (int b = 0; b < 2; ++b) {
+      const size_t base = (size_t)b * H * H;
+      for (int k = 0; k < H; ++k) {
+        const int ks = k >> 2, lk = k & 3;
+        for (int c = 0; c < H; ++c)
+          out[base + ((size_t)((ks >> 1) * 4 + lk) * H + c) * 2 + (ks & 1)] = Q[base + (size_t)k * H + c];
+      }
+    }
+    Q.swap(out);
+  };
   // Engine operand of one extent: forward blocks, then inverse blocks.  The plain engines
   // reduce over the row index of what they read (forward F, inverse F^T); the bfloat16 engines
   // over the column index (forward F^T, inverse F).
   auto sine = [&](int n, int M, bool bf) {
     std::vector<double> f = half(n, M, bf);
-    const std::vector<double> i = half(n, M, !bf);
+    std::vector<double> i = half(n, M, !bf);
+    if (!bf) {
+      pair_rows(f, M);
+      pair_rows(i, M);
+    }
     f.insert(f.end(), i.begin(), i.end());
     return f;
   };

@@ -43,6 +43,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -110,36 +111,43 @@ struct EngPlain {
     (void)M;
     reinterpret_cast<T*>(lds)[k * 17 + c] = v;
   }
-  // Table loads: a wave-uniform base (block, k-step) plus a 32-bit per-lane offset per tile.
+  // Table loads: a wave-uniform base (block, k-step pair) plus a 32-bit per-lane offset per
+  // tile.  The plain tables store each block with k-steps interleaved in pairs: the element
+  // of row 4ks + lk, column c sits at ((ks/2 * 4 + lk) H + c) * 2 + ks % 2, so one 2-element
+  // load brings a lane its operands of k-steps 2P and 2P + 1 (half the load instructions).
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   template <int TPW, int kPD>
   static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
-    const T* Qb = Q + (long long)blk * H * H;
+    const T2* Qb = reinterpret_cast<const T2*>(Q + (long long)blk * H * H);
     int voff[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
-    const int nks = H >> 2;
-    T bq[kPD][TPW];
+    const int npr = H >> 3;           // k-step pairs
+    constexpr int RP = kPD / 2;       // ring depth in pairs
+    T2 bq[RP][TPW];
 #pragma unroll
-    for (int p = 0; p < kPD; ++p)
-      if (p < nks) {
-        const T* Qk = Qb + (long long)(4 * p) * H;
+    for (int p = 0; p < RP; ++p)
+      if (p < npr) {
+        const T2* Qk = Qb + (long long)(4 * p) * H;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
       }
-    for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+    for (int pr0 = 0; pr0 < npr; pr0 += RP) {
 #pragma unroll
-      for (int p = 0; p < kPD; ++p) {
-        const int ks = ks0 + p;
-        if (ks >= nks) break;
-        const T a = Ab[4 * ks];
+      for (int p = 0; p < RP; ++p) {
+        const int pr = pr0 + p;
+        if (pr >= npr) break;
+        const T a0 = Ab[8 * pr], a1 = Ab[8 * pr + 4];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a, bq[p][t], acc[t]);
-        const int kn = ks + kPD;
-        if (kn < nks) {
-          const T* Qk = Qb + (long long)(4 * kn) * H;
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a0, bq[p][t].x, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a1, bq[p][t].y, acc[t]);
+        const int kn = pr + RP;
+        if (kn < npr) {
+          const T2* Qk = Qb + (long long)(4 * kn) * H;
 #pragma unroll
           for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
         }
@@ -151,30 +159,33 @@ struct EngPlain {
                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
-    const T* Qb = Q + (long long)blk * H * H;
+    const T2* Qb = reinterpret_cast<const T2*>(Q + (long long)blk * H * H);
     int voff[TPW];
 #pragma unroll
     for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
-    const int nks = H >> 2;
-    T aq[kPD][TPW];
+    const int npr = H >> 3;
+    constexpr int RP = kPD / 2;
+    T2 aq[RP][TPW];
 #pragma unroll
-    for (int p = 0; p < kPD; ++p)
-      if (p < nks) {
-        const T* Qk = Qb + (long long)(4 * p) * H;
+    for (int p = 0; p < RP; ++p)
+      if (p < npr) {
+        const T2* Qk = Qb + (long long)(4 * p) * H;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
       }
-    for (int ks0 = 0; ks0 < nks; ks0 += kPD) {
+    for (int pr0 = 0; pr0 < npr; pr0 += RP) {
 #pragma unroll
-      for (int p = 0; p < kPD; ++p) {
-        const int ks = ks0 + p;
-        if (ks >= nks) break;
-        const T b = Bb[4 * ks * 17];
+      for (int p = 0; p < RP; ++p) {
+        const int pr = pr0 + p;
+        if (pr >= npr) break;
+        const T b0 = Bb[8 * pr * 17], b1 = Bb[(8 * pr + 4) * 17];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t], b, acc[t]);
-        const int kn = ks + kPD;
-        if (kn < nks) {
-          const T* Qk = Qb + (long long)(4 * kn) * H;
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].x, b0, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].y, b1, acc[t]);
+        const int kn = pr + RP;
+        if (kn < npr) {
+          const T2* Qk = Qb + (long long)(4 * kn) * H;
 #pragma unroll
           for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
         }
