@@ -390,8 +390,9 @@ int build_tables(kktdd_handle* H) {
     return Q;
   };
   // The plain engines read each H x H block with k-steps (groups of four rows) interleaved in
-  // pairs: row 4ks + lk, column c goes to ((ks/2 * 4 + lk) H + c) * 2 + ks % 2.
-  auto pair_rows = [](std::vector<double>& Q, int M) {
+  // groups of kg (2 for float64, 4 for float32): row 4ks + lk, column c goes to
+  // ((ks/kg * 4 + lk) H + c) kg + ks % kg.
+  auto group_rows = [](std::vector<double>& Q, int M, int kg) {
     const int H = M / 2;
     std::vector<double> out(Q.size());
     for (int b = 0; b < 2; ++b) {
@@ -399,20 +400,20 @@ int build_tables(kktdd_handle* H) {
       for (int k = 0; k < H; ++k) {
         const int ks = k >> 2, lk = k & 3;
         for (int c = 0; c < H; ++c)
-          out[base + ((size_t)((ks >> 1) * 4 + lk) * H + c) * 2 + (ks & 1)] = Q[base + (size_t)k * H + c];
+          out[base + ((size_t)((ks / kg) * 4 + lk) * H + c) * kg + (ks % kg)] = Q[base + (size_t)k * H + c];
       }
     }
     Q.swap(out);
   };
   // Engine operand of one extent: forward blocks, then inverse blocks.  The plain engines
   // reduce over the row index of what they read (forward F, inverse F^T); the bfloat16 engines
-  // over the column index (forward F^T, inverse F).
-  auto sine = [&](int n, int M, bool bf) {
+  // over the column index (forward F^T, inverse F).  kg > 0: the plain engines' k-step groups.
+  auto sine = [&](int n, int M, bool bf, int kg) {
     std::vector<double> f = half(n, M, bf);
     std::vector<double> i = half(n, M, !bf);
-    if (!bf) {
-      pair_rows(f, M);
-      pair_rows(i, M);
+    if (kg > 0) {
+      group_rows(f, M, kg);
+      group_rows(i, M, kg);
     }
     f.insert(f.end(), i.begin(), i.end());
     return f;
@@ -427,7 +428,8 @@ int build_tables(kktdd_handle* H) {
     const double s = std::sin(M_PI * (a + 1) / (2.0 * p.ny));
     ly[a] = dtnu * 4.0 / (dy * dy) * s * s;
   }
-  const std::vector<double> Sx = sine(p.nx, g.Mx, false), Sy = sine(p.ny, g.My, false);
+  const std::vector<double> Sx = sine(p.nx, g.Mx, false, 2), Sy = sine(p.ny, g.My, false, 2);
+  const std::vector<double> Sx4 = sine(p.nx, g.Mx, false, 4), Sy4 = sine(p.ny, g.My, false, 4);
   const double norm = 4.0 / ((double)p.nx * p.ny);
   std::vector<double> inv((size_t)g.padded(), 0.0);   // mode order of mode_pos
   for (int q = 0; q < g.my; ++q)
@@ -456,7 +458,7 @@ int build_tables(kktdd_handle* H) {
       a.insert(a.end(), b.begin(), b.end());
       return a;
     };
-    const std::vector<uint16_t> bx = parts2(sine(p.nx, g.Mx, true)), by = parts2(sine(p.ny, g.My, true));
+    const std::vector<uint16_t> bx = parts2(sine(p.nx, g.Mx, true, 0)), by = parts2(sine(p.ny, g.My, true, 0));
     if (int e = dalloc(H, &H->SxBF, bx.size())) return e;
     if (int e = dalloc(H, &H->SyBF, by.size())) return e;
     KKT_HIP(hipMemcpy(H->SxBF, bx.data(), bx.size() * 2, hipMemcpyHostToDevice));
@@ -474,7 +476,7 @@ int build_tables(kktdd_handle* H) {
   KKT_HIP(hipMemcpy(H->Sx64, Sx.data(), Sx.size() * 8, hipMemcpyHostToDevice));
   KKT_HIP(hipMemcpy(H->Sy64, Sy.data(), Sy.size() * 8, hipMemcpyHostToDevice));
   KKT_HIP(hipMemcpy(H->invlam64, inv.data(), inv.size() * 8, hipMemcpyHostToDevice));
-  const auto Sx32 = to32(Sx), Sy32 = to32(Sy), inv32 = to32(inv);
+  const auto Sx32 = to32(Sx4), Sy32 = to32(Sy4), inv32 = to32(inv);
   KKT_HIP(hipMemcpy(H->Sx32, Sx32.data(), Sx32.size() * 4, hipMemcpyHostToDevice));
   KKT_HIP(hipMemcpy(H->Sy32, Sy32.data(), Sy32.size() * 4, hipMemcpyHostToDevice));
   KKT_HIP(hipMemcpy(H->invlam32, inv32.data(), inv32.size() * 4, hipMemcpyHostToDevice));

@@ -112,12 +112,13 @@ struct EngPlain {
     reinterpret_cast<T*>(lds)[k * 17 + c] = v;
   }
   // Table loads: a wave-uniform base (block, k-step pair) plus a 32-bit per-lane offset per
-  // tile.  The plain tables store each block with k-steps interleaved in pairs: the element
-  // of row 4ks + lk, column c sits at ((ks/2 * 4 + lk) H + c) * 2 + ks % 2, so one 2-element
+  // tile.  The float64 tables store each block with k-steps interleaved in pairs: the element
+  // of row 4ks + lk, column c sits at ((ks/2 * 4 + lk) H + c) * 2 + ks % 2, so one 16-byte
   // load brings a lane its operands of k-steps 2P and 2P + 1 (half the load instructions).
+  // The float32 tables group four k-steps the same way (a quarter of the loads).
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   template <int TPW, int kPD>
-  static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
+  static __device__ void gemm_right2(const unsigned char* lds, const T* __restrict__ Q, int M,
                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
@@ -155,7 +156,7 @@ struct EngPlain {
     }
   }
   template <int TPW, int kPD>
-  static __device__ void gemm_left(const T* __restrict__ Q, const unsigned char* lds, int M,
+  static __device__ void gemm_left2(const T* __restrict__ Q, const unsigned char* lds, int M,
                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
     const int H = M >> 1;
     const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
@@ -191,6 +192,106 @@ struct EngPlain {
         }
       }
     }
+  }
+  // float32: k-steps in groups of four, one 16-byte load per lane brings four of them.
+  template <int TPW, int kPD>
+  static __device__ void gemm_right4(const unsigned char* lds, const T* __restrict__ Q, int M,
+                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    const int H = M >> 1;
+    const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
+    const float4* Qb = reinterpret_cast<const float4*>(Q + (long long)blk * H * H);
+    int voff[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
+    const int ngr = H >> 4;                          // groups of four k-steps
+    constexpr int RP = kPD / 4 > 0 ? kPD / 4 : 1;    // ring depth in groups
+    float4 bq[RP][TPW];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+      if (p < ngr) {
+        const float4* Qk = Qb + (long long)(4 * p) * H;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
+      }
+    for (int gr0 = 0; gr0 < ngr; gr0 += RP) {
+#pragma unroll
+      for (int p = 0; p < RP; ++p) {
+        const int gr = gr0 + p;
+        if (gr >= ngr) break;
+        const T a0 = Ab[16 * gr], a1 = Ab[16 * gr + 4], a2 = Ab[16 * gr + 8], a3 = Ab[16 * gr + 12];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a0, bq[p][t].x, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a1, bq[p][t].y, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a2, bq[p][t].z, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a3, bq[p][t].w, acc[t]);
+        const int kn = gr + RP;
+        if (kn < ngr) {
+          const float4* Qk = Qb + (long long)(4 * kn) * H;
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
+        }
+      }
+    }
+  }
+  template <int TPW, int kPD>
+  static __device__ void gemm_left4(const T* __restrict__ Q, const unsigned char* lds, int M,
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    const int H = M >> 1;
+    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
+    const float4* Qb = reinterpret_cast<const float4*>(Q + (long long)blk * H * H);
+    int voff[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) voff[t] = lk * H + (lt0 + t * lts) * 16 + li;
+    const int ngr = H >> 4;
+    constexpr int RP = kPD / 4 > 0 ? kPD / 4 : 1;
+    float4 aq[RP][TPW];
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+      if (p < ngr) {
+        const float4* Qk = Qb + (long long)(4 * p) * H;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
+      }
+    for (int gr0 = 0; gr0 < ngr; gr0 += RP) {
+#pragma unroll
+      for (int p = 0; p < RP; ++p) {
+        const int gr = gr0 + p;
+        if (gr >= ngr) break;
+        const T b0 = Bb[16 * gr * 17], b1 = Bb[(16 * gr + 4) * 17], b2 = Bb[(16 * gr + 8) * 17],
+                b3 = Bb[(16 * gr + 12) * 17];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].x, b0, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].y, b1, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].z, b2, acc[t]);
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].w, b3, acc[t]);
+        const int kn = gr + RP;
+        if (kn < ngr) {
+          const float4* Qk = Qb + (long long)(4 * kn) * H;
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
+        }
+      }
+    }
+  }
+  // Table operand groups: kGroup k-steps per load (two in float64, four in float32).
+  static constexpr int kGroup = sizeof(T) == 8 ? 2 : 4;
+  template <int TPW, int kPD>
+  static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    if constexpr (sizeof(T) == 8) gemm_right2<TPW, kPD>(lds, Q, M, blk, lt0, lts, li, lk, acc);
+    else gemm_right4<TPW, kPD>(lds, Q, M, blk, lt0, lts, li, lk, acc);
+  }
+  template <int TPW, int kPD>
+  static __device__ void gemm_left(const T* __restrict__ Q, const unsigned char* lds, int M,
+                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
+    if constexpr (sizeof(T) == 8) gemm_left2<TPW, kPD>(Q, lds, M, blk, lt0, lts, li, lk, acc);
+    else gemm_left4<TPW, kPD>(Q, lds, M, blk, lt0, lts, li, lk, acc);
   }
 };
 
