@@ -82,7 +82,8 @@ template <int TPW>
 constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
 
 // ---- plain engines (f64, f32) ----------------------------------------------------------
-// A half-transform table Q holds two H x H blocks (H = M/2), block b at Q + b*H*H, row-major.
+// A half-transform table Q holds two H x H blocks (H = M/2), block b at Q + b*H*H, its rows
+// stored in k-step groups (see the table loads below).
 // gemm_right: acc[t] += A(:, half blk) * Q[blk](:, tile),  A = 16 x M operand in LDS.
 // gemm_left:  acc[t] += Q[blk](:, tile)^T * B(half blk, :), B = M x 16 operand in LDS.
 // Output tile t of a wave is local tile lt0 + t*lts of half blk.
