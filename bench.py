@@ -1,24 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the two-level time-DD preconditioned KKT solve on one MI355X.
 
-One step = FGMRES(30) solves, from x0 = 0 to a 1e-8 relative residual, of the grid128
-workload at both of its regularisation parameters: 128x128 intervals (127^2 interior points),
-nt = 256, T = 1, nu = 1, omega in {1e-2, 1e-4}, 16 time subdomains with overlap 2, constant +
-linear coarse basis, seeded sine-mode target (12,387,072 KKT unknowns per problem).  The
-right-hand sides are resident in HBM before the timed region.  `value` is the float64 path;
-the float32-sweep path ("mixed": float32 sine-transform GEMMs and sweep state, float64 outer
-FGMRES, matvec and coarse level) is timed the same way and reported beside it.
+One step = one FGMRES solve, from x0 = 0 to a 1e-8 relative residual, of the grid512 workload
+(the largest that fits one GPU): 512x512 intervals (511^2 interior points), nt = 2048, T = 1,
+nu = 1, omega = 1e-4, 128 time subdomains with overlap 4, constant + linear coarse basis,
+seeded 32-mode sine target; 1,604,327,424 KKT unknowns, FGMRES(12) (a 30-vector basis does not
+fit in 288 GB).  The right-hand side is resident in HBM before the timed region.  `value` is
+the float64 path (every step of the method in float64); the mixed paths (sweeps and their
+sine-transform GEMMs in float32 or split bfloat16, FGMRES, matvec, Arnoldi and coarse level in
+float64) are timed the same way and reported beside it with their ratio to float64.
+--workload selects the other workloads (grid128 pair, grid256, the uneven batch of 64).
 
 Prints one JSON line.  Extra objects:
-  roofline      the kernel class with the largest share of the float64 solve time, its
-                algorithmic bytes (or flops) over its launch durations, timed with HIP events
+  roofline      the kernel class with the largest share of the float64 solve time (the sweep
+                pair, row and column transform kernels together, counts as one class), its
+                algorithmic flops (or bytes) over its launch durations, timed with HIP events
                 on one extra step whose solves run one after another, against the MI355X
                 peak; traffic from rocprofv3 counters when recorded
+  mixed         per inner precision: unknowns/s, ratio to float64, iterations, residuals per
+                block, distance from the float64 solution, whether it is accepted (see
+                accept()), and its own kernel classes
   cpu_baseline  the float64 CPU oracle timed on this host on a bounded sample of the same
                 workload (the first FGMRES iterations), scaled to a whole solve
   hoisted       the same step with the transform-hoisted Schur block (sweeps as scalar
                 recurrences per sine mode between one forward and one inverse batched
                 transform), float64 and float32 transforms
+  setup_s       kkt_create wall time per problem (tables, coarse factors, autotuned shapes)
 """
 
 import argparse
@@ -32,7 +39,10 @@ sys.path.insert(0, ROOT)
 
 METRIC = "KKT space-time unknowns solved/s to 1e-8 rel. residual, mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
-MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# dense MFMA peaks; a split-bfloat16 engine issues 1, 3 or 6 bf16 part products per
+# algorithmic product, so its peak in algorithmic flops is the bf16 peak over that count
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "bf16x3": 2500.0 / 3,
+                    "bf16x6": 2500.0 / 6}
 WORKLOAD_SETS = {
     # the problems one step solves (one batch)
     "grid128": ("grid128", "grid128_w4"),
@@ -44,8 +54,12 @@ WORKLOAD_SETS = {
 DEFAULT_RESTART = {"grid512": 12, "uneven64": 12}
 # reduced-precision paths timed per workload (the largest ones time a subset)
 # ("auto": float32 sweeps per problem where kappa(D_sigma) <= 500, else float64)
-DEFAULT_MIXED = {"grid512": ("fp32", "bf16x6"), "uneven64": ("auto",)}
+DEFAULT_MIXED = {"grid512": ("fp32", "bf16x6", "bf16x3"), "uneven64": ("auto",)}
 DEFAULT_HOISTED = {"grid512": ("fp64", "fp32"), "uneven64": ("fp64", "auto")}
+# A mixed result counts toward the mixed-vs-float64 ratio only if it meets the same stopping
+# test and leaves its u-block residual within this factor of the float64 solution's: the
+# whole-vector test is dominated by the w block, so a solution can pass it with a loose u block.
+ACCEPT_U_FACTOR = 100.0
 
 
 def workload_problems(key):
@@ -77,11 +91,21 @@ TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.83e6},
            "grid512": {"arnoldi": 34507.54e6, "matvec": 31325.91e6}}
 
 
+def progress(msg):
+    """One line per finished leg on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--leg-steps", type=int, default=2,
+                    help="timed steps of each mixed and hoisted path (the float64 path times --steps)")
+    ap.add_argument("--leg-warmup", type=int, default=1, help="warm-up steps of each mixed and hoisted path")
+    ap.add_argument("--mixed", default=None,
+                    help="comma-separated inner precisions of the mixed legs (default per workload)")
     ap.add_argument("--restart", type=int, default=None,
                     help="FGMRES restart length (default 30; 12 for grid512 and uneven64)")
     ap.add_argument("--rtol", type=float, default=1e-8)
@@ -94,10 +118,10 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy 1 GiB device-to-device once (a known-size kernel for HBM counters)")
     ap.add_argument("--roofline-class", default=None,
-                    choices=["matvec", "sweep_rows", "sweep_cols", "coarse", "arnoldi", "other"],
+                    choices=["matvec", "sweeps", "sweep_rows", "sweep_cols", "coarse", "arnoldi", "other"],
                     help="kernel class of the roofline object (default: the one with the most time)")
-    ap.add_argument("--workload", default="grid128", choices=sorted(WORKLOAD_SETS),
-                    help="problem set of one step (default: grid128 at omega 1e-2 and 1e-4)")
+    ap.add_argument("--workload", default="grid512", choices=sorted(WORKLOAD_SETS),
+                    help="problem set of one step (default: grid512)")
     return ap.parse_args()
 
 
@@ -128,6 +152,7 @@ def main():
         recipes[name] = recipe
         probs.append((name, params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
         del u0, ut
+    progress(f"inputs of {len(probs)} problem(s) resident on the device")
     unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
 
     def run_path(precision, steps, warmup, profile, sweep="step", must_converge=True, keep_x=False):
@@ -157,6 +182,8 @@ def main():
             stats = step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        progress(f"{precision} {sweep}: {steps} timed steps, {1e3 * dt / max(steps, 1):.1f} ms per step, "
+                 f"iterations {[st['iters'] for st in stats]}")
         prof = None
         if profile:
             # Kernel timer: the same step once more, its solves one after another, with HIP
@@ -174,16 +201,18 @@ def main():
                     for kk in acc:
                         acc[kk] += v[kk]
                 S.profile(False)
+        setup = {name: st["setup_s"] for (name, _, _, _), st in zip(probs, stats)}
         for S in solvers:
             S.close()
-        return dt, stats, prof, (xs if keep_x else None)
+        return dt, stats, prof, (xs if keep_x else None), setup
 
     # float64 path; its solutions (host copies) are the reference of the other paths' errors
     others = not (args.no_mixed and args.no_hoisted)
-    dt64, st64, prof64, xs64 = run_path("fp64", args.steps, args.warmup, profile=True, keep_x=others)
+    dt64, st64, prof64, xs64, setup64 = run_path("fp64", args.steps, args.warmup, profile=True, keep_x=others)
     x64 = [x.cpu() for x in xs64] if others else None
     del xs64
     value64 = args.steps * sum(unknowns) / dt64
+    names = [name for name, _, _, _ in probs]
     result = {
         "metric": METRIC, "value": value64, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt64 / args.steps, "higher_is_better": True,
@@ -191,77 +220,114 @@ def main():
         "config": {"workload": DESCRIPTIONS[args.workload] + ", FGMRES(%d) to %g from x0=0, %s" % (
                                    args.restart, args.rtol,
                                    "solved one after another" if args.sequential else "solved as one batch"),
-                   "unknowns_per_step": sum(unknowns), "problems": [name for name, _, _, _ in probs]},
-        "iterations": {name: st["iters"] for (name, _, _, _), st in zip(probs, st64)},
-        "reorthogonalised_steps": {name: st["reorth"] for (name, _, _, _), st in zip(probs, st64)},
+                   "unknowns_per_step": sum(unknowns), "problems": names},
+        "iterations": {name: st["iters"] for name, st in zip(names, st64)},
+        "reorthogonalised_steps": {name: st["reorth"] for name, st in zip(names, st64)},
         "batched": not args.sequential,
-        "relres_true": {name: st["relres_true"] for (name, _, _, _), st in zip(probs, st64)},
+        "relres_true": {name: st["relres_true"] for name, st in zip(names, st64)},
         # ||f_b - (K x)_b|| / ||f_b|| per block (u, z, w; 0 where f_b = 0)
-        "relres_block": {name: st["relres_block"] for (name, _, _, _), st in zip(probs, st64)},
+        "relres_block": {name: st["relres_block"] for name, st in zip(names, st64)},
+        # kkt_create wall time per problem (outside the timed region)
+        "setup_s": setup64,
     }
 
-    # roofline of the dominant kernel class (or the one asked for)
-    def class_roof(cls):
-        d = prof64[cls]
-        if cls in ("sweep_rows", "sweep_cols"):
+    # kernel classes: the row and column transform kernels of the sweeps form one class (they
+    # alternate within every sweep step), reported also separately
+    def merged(prof):
+        out = dict(prof)
+        rows, cols = prof["sweep_rows"], prof["sweep_cols"]
+        out["sweeps"] = {k: rows[k] + cols[k] for k in rows}
+        return out
+
+    def class_roof(prof, cls, prec):
+        d = prof[cls]
+        if cls in ("sweeps", "sweep_rows", "sweep_cols"):
             achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12 if d["ms"] else 0.0
-            r = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS["fp64"], "unit": "TFLOP/s"}
+            r = {"bound": "mfma", "achieved": achieved, "peak": MFMA_PEAK_TFLOPS[prec], "unit": "TFLOP/s"}
         else:
             achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9 if d["ms"] else 0.0
             r = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         r["frac"] = r["achieved"] / r["peak"]
         return r
 
-    dom = args.roofline_class or max(prof64, key=lambda k: prof64[k]["ms"])
-    d = prof64[dom]
-    total_ms = sum(v["ms"] for v in prof64.values())
-    roof = class_roof(dom)
+    def classes(prof, prec):
+        prof = merged(prof)
+        total = sum(v["ms"] for k, v in prof.items() if k != "sweeps")
+        out = {}
+        for k, v in prof.items():
+            if v["launches"]:
+                r = class_roof(prof, k, prec)
+                out[k] = {"launches": v["launches"], "ms_per_step": v["ms"],
+                          "share_of_kernel_time": v["ms"] / total if total else None,
+                          "avg_launch_us": 1e3 * v["ms"] / v["launches"],
+                          "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
+        return out
+
+    # roofline of the dominant kernel class (or the one asked for)
+    prof = merged(prof64)
+    cand = [k for k in prof if k not in ("sweep_rows", "sweep_cols")]
+    dom = args.roofline_class or max(cand, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    total_ms = sum(v["ms"] for k, v in prof.items() if k != "sweeps")
+    roof = class_roof(prof, dom, "fp64")
     roof["traffic"] = TRAFFIC.get(args.workload, {}).get(dom)
     roof["kernel_class"] = dom
+    if dom == "sweeps":
+        roof["kernels"] = "k_rows + k_cols (float64 engine): two chained folded sine-transform products each"
     roof["launches"] = d["launches"]
     roof["avg_launch_us"] = 1e3 * d["ms"] / max(d["launches"], 1)
     roof["algorithmic_bytes_per_launch"] = d["bytes"] / max(d["launches"], 1)
     roof["algorithmic_flops_per_launch"] = d["flops"] / max(d["launches"], 1)
     roof["share_of_kernel_time"] = d["ms"] / total_ms if total_ms else None
-    roof["classes_ms_per_step"] = {k: v["ms"] for k, v in prof64.items()}
-    roof["classes"] = {}
-    for k, v in prof64.items():
-        if v["launches"]:
-            r = class_roof(k)
-            roof["classes"][k] = {"launches": v["launches"], "avg_launch_us": 1e3 * v["ms"] / v["launches"],
-                                  "achieved": r["achieved"], "unit": r["unit"], "frac": r["frac"]}
+    roof["classes"] = classes(prof64, "fp64")
     roof["timed_on"] = "one extra step, its solves run one after another, HIP events around every launch"
     result["roofline"] = roof
 
     def err_vs_fp64(xs):
         # relative 2-norm distance of each solution from the float64 per-step path's
         out = {}
-        for (name, _, _, _), x, ref in zip(probs, xs, x64):
+        for name, x, ref in zip(names, xs, x64):
             r = ref.to(dev)
             out[name] = float((x - r).norm() / r.norm())
             del r
         return out
 
+    def accept(st):
+        # the same stopping test as float64, and a u-block residual no looser than
+        # ACCEPT_U_FACTOR times the float64 solution's on the same problem
+        return all(x["status"] == 0 and x["relres_true"] <= args.rtol and
+                   x["relres_block"][0] <= ACCEPT_U_FACTOR * max(ref["relres_block"][0], args.rtol)
+                   for x, ref in zip(st, st64))
+
     def summary(prec, sweep):
-        dt, st, _, xs = run_path(prec, args.steps, args.warmup, profile=False, sweep=sweep,
-                                 must_converge=False, keep_x=True)
+        dt, st, profx, xs, setup = run_path(prec, args.leg_steps, args.leg_warmup, profile=True, sweep=sweep,
+                                            must_converge=False, keep_x=True)
         err = err_vs_fp64(xs)
         del xs
-        failed = [name for (name, _, _, _), x in zip(probs, st) if x["status"] != 0]
+        out = {"ms_per_step": 1e3 * dt / args.leg_steps, "steps": args.leg_steps, "warmup": args.leg_warmup,
+               "iterations": {name: x["iters"] for name, x in zip(names, st)},
+               "relres_true": {name: x["relres_true"] for name, x in zip(names, st)},
+               "relres_block": {name: x["relres_block"] for name, x in zip(names, st)},
+               "err_vs_fp64": err, "setup_s": setup, "accepted": accept(st),
+               "classes": classes(profx, prec if prec in MFMA_PEAK_TFLOPS else "fp64")}
+        failed = [name for name, x in zip(names, st) if x["status"] != 0]
         if failed:
-            return {"value": None, "not_converged": failed, "ms_per_step": 1e3 * dt / args.steps,
-                    "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
-                    "err_vs_fp64": err}
-        v = args.steps * sum(unknowns) / dt
-        return {"value": v, "ms_per_step": 1e3 * dt / args.steps, "ratio_vs_fp64": v / value64,
-                "iterations": {name: x["iters"] for (name, _, _, _), x in zip(probs, st)},
-                "relres_true": {name: x["relres_true"] for (name, _, _, _), x in zip(probs, st)},
-                "err_vs_fp64": err}
+            out.update(value=None, ratio_vs_fp64=None, not_converged=failed)
+            return out
+        v = args.leg_steps * sum(unknowns) / dt
+        out.update(value=v, ratio_vs_fp64=v / value64)
+        return out
 
     if not args.no_mixed:
-        # reduced-precision sweeps and sine-transform GEMMs; FGMRES, matvec and coarse level
-        # stay float64 (FGMRES acting as iterative refinement)
-        result["mixed"] = {prec: summary(prec, "step") for prec in DEFAULT_MIXED.get(args.workload, MIXED)}
+        # reduced-precision sweeps and sine-transform GEMMs; FGMRES, matvec, Arnoldi and coarse
+        # level stay float64 (FGMRES acting as iterative refinement)
+        legs = args.mixed.split(",") if args.mixed else DEFAULT_MIXED.get(args.workload, MIXED)
+        result["mixed"] = {prec: summary(prec, "step") for prec in legs}
+        ok = {k: v for k, v in result["mixed"].items() if v["accepted"] and v["value"]}
+        if ok:
+            best = max(ok, key=lambda k: ok[k]["value"])
+            result["mixed_best"] = {"precision": best, "value": ok[best]["value"],
+                                    "ratio_vs_fp64": ok[best]["ratio_vs_fp64"]}
 
     if not args.no_hoisted:
         # transform-hoisted Schur block (sine-mode sweeps), measured beside the per-step path

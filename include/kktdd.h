@@ -116,6 +116,8 @@ typedef struct kktdd_stats {
   double relres_true;     /* ||f - K x|| / ||f|| at exit                                   */
   double relres_block[3]; /* per-block ||f_b - (K x)_b|| / ||f_b|| (u, z, w; 0 if f_b = 0) */
   double solve_s;         /* wall time of the solve                                        */
+  double setup_s;         /* wall time of kkt_create for this handle: tables, coarse
+                             factors, work buffers and the launch-shape measurements        */
 } kktdd_stats;
 
 typedef struct kktdd_handle kktdd_handle;
@@ -205,6 +207,13 @@ int fgmres_solve(kktdd_handle* h, const double* f, double* x, int32_t restart, i
 int kkt_solve_batched(int32_t n, kktdd_handle* const* hs, const double* const* f,
                       double* const* x, int32_t restart, int32_t maxit, double rtol,
                       kktdd_stats* stats);
+
+/* Residual history of the handle's last fgmres_solve (or kkt_solve_batched member): the
+ * rotated estimate |g_{j+1}| / ||f|| after every Arnoldi step, over all cycles (Sec. 4's
+ * stopping quantity).  Copies min(count, cap) values to out (host memory) and returns the
+ * count, or KKTDD_EINVAL for a NULL handle, cap < 0, or out NULL with cap > 0.  Host-only.
+ * With the environment variable KKTDD_LOG=1 every solve also prints it to stderr. */
+int kkt_residual_history(const kktdd_handle* h, double* out, int32_t cap);
 
 /* Kernel classes of the per-launch timer below. */
 enum kktdd_kernel_class {

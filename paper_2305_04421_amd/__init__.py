@@ -150,6 +150,14 @@ class KKTSolver:
             out[name] = dict(ms=ms.value, launches=n.value, bytes=b.value, flops=f.value)
         return out
 
+    def residual_history(self):
+        """Rotated residual estimates |g_{j+1}|/||f|| after every Arnoldi step of the last solve."""
+        lib = _lib.load()
+        n = _lib.check(lib.kkt_residual_history(self._h, None, 0), "kkt_residual_history")
+        buf = (ctypes.c_double * max(n, 1))()
+        _lib.check(lib.kkt_residual_history(self._h, buf, n), "kkt_residual_history")
+        return list(buf[:n])
+
     def solve(self, f, x=None, restart=30, maxit=500, rtol=1e-8):
         """FGMRES(restart) from x (zero if None); returns (x, stats dict)."""
         import torch

@@ -33,7 +33,7 @@ MAX_RESTART = 1024
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_precision",
             "kkt_kappa", "kkt_tune_set", "kkt_tune_get", "kkt_rhs",
             "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
-            "kkt_profile_read", "kkt_last_error")
+            "kkt_profile_read", "kkt_residual_history", "kkt_last_error")
 
 # enum kktdd_kernel_class
 KERNEL_CLASSES = ("matvec", "sweep_rows", "sweep_cols", "coarse", "arnoldi", "other")
@@ -54,12 +54,13 @@ class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32),
                 ("status", ctypes.c_int32), ("reorth", ctypes.c_int32),
                 ("relres_est", ctypes.c_double), ("relres_true", ctypes.c_double),
-                ("relres_block", ctypes.c_double * 3), ("solve_s", ctypes.c_double)]
+                ("relres_block", ctypes.c_double * 3), ("solve_s", ctypes.c_double),
+                ("setup_s", ctypes.c_double)]
 
     def as_dict(self):
         return dict(iters=self.iters, restarts=self.restarts, status=self.status, reorth=self.reorth,
                     relres_est=self.relres_est, relres_true=self.relres_true,
-                    relres_block=list(self.relres_block), solve_s=self.solve_s)
+                    relres_block=list(self.relres_block), solve_s=self.solve_s, setup_s=self.setup_s)
 
 
 _lib = None
@@ -98,6 +99,8 @@ def load():
     lib.kkt_profile.argtypes = [vp, ctypes.c_int]
     lib.kkt_profile_read.argtypes = [vp, ctypes.c_int, ctypes.POINTER(dbl), ctypes.POINTER(ctypes.c_int64),
                                      ctypes.POINTER(dbl), ctypes.POINTER(dbl)]
+    lib.kkt_residual_history.argtypes = [vp, ctypes.POINTER(dbl), i32]
+    lib.kkt_residual_history.restype = ctypes.c_int
     lib.kkt_last_error.argtypes = []
     lib.kkt_last_error.restype = ctypes.c_char_p
     for name in ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_tune_set", "kkt_tune_get", "kkt_rhs", "kkt_apply",

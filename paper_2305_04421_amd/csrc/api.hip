@@ -3,6 +3,7 @@
 // Owns the handle (tables, work buffers, Krylov storage), validates problems, plans memory,
 // orchestrates the preconditioner (Eqs. (7), (13)-(15)) and runs flexible GMRES (Sec. 4).
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <chrono>
 #include <cmath>
@@ -34,6 +35,44 @@ constexpr long kBatchStaggerUs = 300;   // start offset of the odd members of a 
 constexpr int kFieldSums = 3;      // per-block partial sums of a field reduction
 constexpr int kMaxCgsRestart = 31; // the CGS passes keep one accumulator per basis vector
 constexpr double kReorthEta = 0.70710678118654752;  // 1/sqrt(2)
+
+// KKTDD_ROCTX=1: a roctx range around every kernel launch (named by its timer class) and
+// around every entry point, for rocprofv3 --marker-trace.  Read once per process.
+bool roctx_enabled() {
+  static const bool v = [] {
+    const char* e = std::getenv("KKTDD_ROCTX");
+    return e && std::atoi(e) != 0;
+  }();
+  return v;
+}
+const char* const kClassNames[KKTDD_K_COUNT] = {"kktdd:matvec", "kktdd:sweep_rows", "kktdd:sweep_cols",
+                                                "kktdd:coarse", "kktdd:arnoldi", "kktdd:other"};
+
+// KKTDD_DEBUG_POISON=1: every device buffer the library allocates is filled with NaN bytes,
+// and the work buffers of the preconditioner and of FGMRES are filled again at the start of
+// every precond_apply and fgmres_solve.  A kernel that reads workspace it has not written
+// first then produces NaN.  Read at every use, so a process can switch it.
+bool poison_enabled() {
+  const char* e = std::getenv("KKTDD_DEBUG_POISON");
+  return e && std::atoi(e) != 0;
+}
+
+// KKTDD_LOG=1: every fgmres_solve prints its residual-estimate history to stderr when it ends.
+bool log_enabled() {
+  const char* e = std::getenv("KKTDD_LOG");
+  return e && std::atoi(e) != 0;
+}
+
+// RAII roctx range (no-op unless KKTDD_ROCTX=1).
+struct RoctxScope {
+  bool on;
+  explicit RoctxScope(const char* name) : on(roctx_enabled()) {
+    if (on) roctxRangePushA(name);
+  }
+  ~RoctxScope() {
+    if (on) roctxRangePop();
+  }
+};
 }  // namespace
 
 int set_error(int code, const std::string& msg) {
@@ -47,33 +86,13 @@ int hip_fail(hipError_t e, const char* what, const char* file, int line) {
   return set_error(KKTDD_EHIP, buf);
 }
 
-// ---- per-launch timer ------------------------------------------------------------------
-struct Prof {
-  bool on = false;
-  std::vector<hipEvent_t> pool;   // events are created once and reused
-  size_t used = 0;
-  struct Rec { int cls; size_t ev; double bytes, flops; };
-  std::vector<Rec> recs;
-  size_t open_ev = 0;
-  hipEvent_t next() {
-    if (used == pool.size()) {
-      hipEvent_t e = nullptr;
-      if (hipEventCreate(&e) != hipSuccess) {
-        (void)hipGetLastError();
-        return nullptr;
-      }
-      pool.push_back(e);
-    }
-    return pool[used++];
-  }
-};
 
 namespace {
 thread_local Prof* t_prof = nullptr;
 }
 
 void prof_begin(int kclass, hipStream_t s) {
-  (void)kclass;
+  if (roctx_enabled() && kclass >= 0 && kclass < KKTDD_K_COUNT) roctxRangePushA(kClassNames[kclass]);
   if (!t_prof || !t_prof->on) return;
   hipEvent_t e = t_prof->next();
   if (!e) return;
@@ -82,6 +101,7 @@ void prof_begin(int kclass, hipStream_t s) {
 }
 
 void prof_end(int kclass, hipStream_t s, double bytes, double flops) {
+  if (roctx_enabled() && kclass >= 0 && kclass < KKTDD_K_COUNT) roctxRangePop();
   if (!t_prof || !t_prof->on) return;
   hipEvent_t e = t_prof->next();
   if (!e) return;
@@ -100,61 +120,6 @@ void prof_add_bytes(long long record, double bytes) {
 
 using namespace kktdd;
 
-struct kktdd_handle {
-  kktdd_problem prob{};
-  Geom g{};
-  hipStream_t stream = nullptr;
-  int device = 0;
-  int elem = 8;                       // bytes per element of the sweep work buffers
-  std::vector<void*> allocations;
-
-  // tables: per extent the forward then inverse half-transform blocks (see dst.hip), and
-  // the inverse eigenvalues in the folded mode order
-  double *Sx64 = nullptr, *Sy64 = nullptr, *invlam64 = nullptr;
-  float *Sx32 = nullptr, *Sy32 = nullptr, *invlam32 = nullptr;
-  double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
-  // per-step sweeps
-  void *Tbuf = nullptr, *Ubuf = nullptr, *Ybuf = nullptr;
-  double* rprime = nullptr;
-  // modal (transform-hoisted) sweeps
-  void *Rhat = nullptr, *Mtmp = nullptr;
-  double* Ysc = nullptr;
-  double* ext = nullptr;                       // additive-Schwarz extension values
-  // coarse
-  double *r0 = nullptr, *c0 = nullptr, *Dc0 = nullptr, *DDc0 = nullptr;
-  double *chat = nullptr, *ctmp = nullptr, *cfac = nullptr;
-  // reductions
-  double *partials = nullptr, *sums = nullptr;
-  double* host_sums = nullptr;                 // pinned
-  // Krylov basis and its bookkeeping, sized for restart length R (see krylov_small)
-  int R = 0;
-  double *V = nullptr, *Zw = nullptr;
-  double *kpart = nullptr, *ksums = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
-  int* gate = nullptr;
-  double* host_hcol = nullptr;                 // pinned, KrylovSmall(R).host doubles
-  Prof prof;
-
-  uint16_t *SxBF = nullptr, *SyBF = nullptr;  // three bfloat16 parts of each table (transposed blocks)
-
-  // half-transform tables and eigenvalue table of the handle's GEMM engine
-  const void* Sx() const {
-    switch (prob.precision) {
-      case KKTDD_FP64: return Sx64;
-      case KKTDD_FP32: return Sx32;
-      default: return SxBF;
-    }
-  }
-  const void* Sy() const {
-    switch (prob.precision) {
-      case KKTDD_FP64: return Sy64;
-      case KKTDD_FP32: return Sy32;
-      default: return SyBF;
-    }
-  }
-  const void* invlam() const {
-    return prob.precision == KKTDD_FP64 ? (const void*)invlam64 : (const void*)invlam32;
-  }
-};
 
 namespace {
 
@@ -180,6 +145,12 @@ int dalloc(kktdd_handle* h, T** p, size_t count) {
   }
   h->allocations.push_back(q);
   *p = static_cast<T*>(q);
+  if (poison_enabled()) {
+    if (hipMemsetAsync(q, 0xFF, count * sizeof(T), h->stream) != hipSuccess) {
+      (void)hipGetLastError();
+      return set_error(KKTDD_EHIP, "poisoning a new buffer failed");
+    }
+  }
   return 0;
 }
 
@@ -614,6 +585,42 @@ int schur_apply(kktdd_handle* H, const double* rw, const double* dscale, double*
                        H->Tbuf, H->Ubuf, H->Ybuf, s);
 }
 
+// KKTDD_DEBUG_POISON: NaN bytes into every work buffer that a kernel must write before it
+// reads it (not the tables, the coarse factors, or the coarse mode slots whose padding must
+// stay zero).  Stream-ordered before the work that follows.
+int poison_workspace(kktdd_handle* H) {
+  if (!poison_enabled()) return 0;
+  const Geom& g = H->g;
+  const size_t MM = (size_t)g.padded(), el = H->elem;
+  auto fill = [&](void* p, size_t bytes) -> int {
+    if (!p || !bytes) return 0;
+    KKT_HIP(hipMemsetAsync(p, 0xFF, bytes, H->stream));
+    return 0;
+  };
+  if (int e = fill(H->Tbuf, (size_t)g.nd * MM * el)) return e;
+  if (int e = fill(H->Ubuf, (size_t)g.nd * MM * el)) return e;
+  if (int e = fill(H->Ybuf, (size_t)g.nd * g.L * MM * el)) return e;
+  if (int e = fill(H->rprime, (size_t)g.P * 8)) return e;
+  if (int e = fill(H->Rhat, (size_t)g.nt * MM * el)) return e;
+  if (int e = fill(H->Mtmp, (size_t)g.nt * MM * el)) return e;
+  if (int e = fill(H->Ysc, modal_store(g) * 8)) return e;
+  if (int e = fill(H->ext, modal_ext(g) * 8)) return e;
+  for (double* p : {H->r0, H->c0, H->Dc0, H->DDc0})
+    if (int e = fill(p, (size_t)g.nc * g.nxy * 8)) return e;
+  if (int e = fill(H->partials, (size_t)kRedBlocks * kFieldSums * 8)) return e;
+  if (H->R > 0) {
+    const KrylovSmall ks(H->R);
+    if (int e = fill(H->V, (size_t)(H->R + 1) * (size_t)krylov_ld(g) * 8)) return e;
+    if (int e = fill(H->Zw, (size_t)H->R * (size_t)g.P * 8)) return e;
+    if (int e = fill(H->kpart, ks.part * 8)) return e;
+    if (int e = fill(H->ksums, ks.sums * 8)) return e;
+    if (int e = fill(H->hcol, ks.rec * 8)) return e;
+    if (int e = fill(H->vinv, ks.vinv * 8)) return e;
+    if (int e = fill(H->ydev, ks.ydev * 8)) return e;
+  }
+  return 0;
+}
+
 // squared norms of the three fields of a KKT vector, to the host (synchronises)
 int field_sumsq(kktdd_handle* H, const double* r, double out[3]) {
   if (int e = launch_sumsq_blocks(H->g, r, H->partials, kRedBlocks, H->stream)) return e;
@@ -723,6 +730,7 @@ int kkt_memory_plan(const kktdd_problem* prob, int32_t restart, size_t* bytes) {
 }
 
 int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** out) {
+  const auto t_setup = std::chrono::steady_clock::now();
   if (!out) return set_error(KKTDD_EINVAL, "out is NULL");
   *out = nullptr;
   if (int e = validate(prob_in)) return e;
@@ -808,6 +816,7 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     (void)hipGetLastError();
     return fail(set_error(KKTDD_EHIP, "setup failed"));
   }
+  H->setup_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_setup).count();
   *out = H;
   return KKTDD_OK;
 }
@@ -858,8 +867,10 @@ int kkt_apply(kktdd_handle* H, const double* x, double* y) {
 
 int precond_apply(kktdd_handle* H, const double* r, double* z) {
   ProfScope ps(H);
+  RoctxScope rs("kktdd:precond_apply");
   if (!H || !r || !z) return set_error(KKTDD_EINVAL, "NULL argument");
   if (r == z) return set_error(KKTDD_EINVAL, "r and z must not alias");
+  if (int e = poison_workspace(H)) return e;
   const Geom& g = H->g;
   if (int e = launch_scale(g.P, r, 1.0 / g.h, nullptr, z, H->stream)) return e;
   if (int e = launch_scale(g.P, r + g.P, 1.0 / (g.omega * g.h), nullptr, z + g.P, H->stream)) return e;
@@ -918,8 +929,10 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
                  double rtol, kktdd_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   ProfScope ps(H);
+  RoctxScope rs("kktdd:fgmres_solve");
   if (!H || !f || !x) return set_error(KKTDD_EINVAL, "NULL argument");
   if (f == x) return set_error(KKTDD_EINVAL, "f and x must not alias");
+  H->history.clear();
   const bool dcgs = arnoldi_dcgs2();
   if (restart < 1 || restart > KKTDD_MAX_RESTART || maxit < 0 || !(rtol > 0.0))
     return set_error(KKTDD_EINVAL, "need 1 <= restart <= KKTDD_MAX_RESTART, maxit >= 0, rtol > 0");
@@ -931,6 +944,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
   const long long n3 = 3 * g.P;
   const int nred = krylov_blocks(g);
   if (int e = ensure_krylov(H, restart)) return e;
+  if (int e = poison_workspace(H)) return e;
   double fb[3];
   if (int e = field_sumsq(H, f, fb)) return e;
   const double fnorm = std::sqrt(fb[0] + fb[1] + fb[2]);
@@ -941,7 +955,20 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
     st.relres_true = fnorm > 0 ? rn / fnorm : 0.0;
     for (int b = 0; b < 3; ++b) st.relres_block[b] = fb[b] > 0 ? std::sqrt(rb[b] / fb[b]) : 0.0;
     st.solve_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    st.setup_s = H->setup_s;
     if (stats) *stats = st;
+    if (log_enabled()) {
+      std::string line = "kktdd: fgmres_solve status " + std::to_string(status) + ", " +
+                         std::to_string(st.iters) + " iterations, residual estimates";
+      char buf[32];
+      for (double v : H->history) {
+        std::snprintf(buf, sizeof buf, " %.3e", v);
+        line += buf;
+      }
+      std::snprintf(buf, sizeof buf, "; true %.3e\n", st.relres_true);
+      line += buf;
+      std::fputs(line.c_str(), stderr);
+    }
     return status;
   };
   if (!(std::isfinite(fnorm))) {
@@ -1081,6 +1108,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
         ++its;
         m = j + 1;
         est = std::fabs(gv[j + 1]) / fnorm;
+        H->history.push_back(est);
         if (std::fabs(gv[j + 1]) <= tol || its >= maxit || sub == 0.0) break;
         continue;
       }
@@ -1107,6 +1135,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
         Hm[(size_t)j * R + (j - 1)] = nu * al;
         rotate_column(j - 1);
         est = std::fabs(gv[j]) / fnorm;
+        H->history.push_back(est);
       }
       alpha[j] = al;
       for (int i = 0; i < j; ++i) amat[(size_t)i * (R + 1) + j] = hrec[2 + i];
@@ -1139,6 +1168,7 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       }
       rotate_column(j);
       est = std::fabs(gv[j + 1]) / fnorm;
+      H->history.push_back(est);
       m = j + 1;
       break;
     }
@@ -1235,6 +1265,13 @@ int kkt_solve_batched(int32_t n, kktdd_handle* const* hs, const double* const* f
     }
   }
   return worst;
+}
+
+int kkt_residual_history(const kktdd_handle* H, double* out, int32_t cap) {
+  if (!H || cap < 0 || (cap > 0 && !out)) return set_error(KKTDD_EINVAL, "bad history arguments");
+  const int n = (int)H->history.size();
+  for (int i = 0; i < n && i < cap; ++i) out[i] = H->history[i];
+  return n;
 }
 
 int kkt_profile(kktdd_handle* H, int enable) {

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "kktdd.h"
 
@@ -193,4 +194,85 @@ int launch_dcgs_update(long long n, double* V, long long ldv, int j, const doubl
 int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
                         hipStream_t s);
 
+// ---- per-launch timer ------------------------------------------------------------------
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;   // events are created once and reused
+  size_t used = 0;
+  struct Rec { int cls; size_t ev; double bytes, flops; };
+  std::vector<Rec> recs;
+  size_t open_ev = 0;
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+      }
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
 }  // namespace kktdd
+
+// Handle of one problem (opaque in the C ABI): its geometry, stream, tables and buffers.
+struct kktdd_handle {
+  kktdd_problem prob{};
+  kktdd::Geom g{};
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int elem = 8;                       // bytes per element of the sweep work buffers
+  double setup_s = 0.0;               // wall time of kkt_create
+  std::vector<double> history;        // residual estimates of the last fgmres_solve
+  std::vector<void*> allocations;
+
+  // tables: per extent the forward then inverse half-transform blocks (see dst.hip), and
+  // the inverse eigenvalues in the folded mode order
+  double *Sx64 = nullptr, *Sy64 = nullptr, *invlam64 = nullptr;
+  float *Sx32 = nullptr, *Sy32 = nullptr, *invlam32 = nullptr;
+  double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
+  // per-step sweeps
+  void *Tbuf = nullptr, *Ubuf = nullptr, *Ybuf = nullptr;
+  double* rprime = nullptr;
+  // modal (transform-hoisted) sweeps
+  void *Rhat = nullptr, *Mtmp = nullptr;
+  double* Ysc = nullptr;
+  double* ext = nullptr;                       // additive-Schwarz extension values
+  // coarse
+  double *r0 = nullptr, *c0 = nullptr, *Dc0 = nullptr, *DDc0 = nullptr;
+  double *chat = nullptr, *ctmp = nullptr, *cfac = nullptr;
+  // reductions
+  double *partials = nullptr, *sums = nullptr;
+  double* host_sums = nullptr;                 // pinned
+  // Krylov basis and its bookkeeping, sized for restart length R (see krylov_small)
+  int R = 0;
+  double *V = nullptr, *Zw = nullptr;
+  double *kpart = nullptr, *ksums = nullptr, *hcol = nullptr, *vinv = nullptr, *ydev = nullptr;
+  int* gate = nullptr;
+  double* host_hcol = nullptr;                 // pinned, KrylovSmall(R).host doubles
+  kktdd::Prof prof;
+
+  uint16_t *SxBF = nullptr, *SyBF = nullptr;  // three bfloat16 parts of each table (transposed blocks)
+
+  // half-transform tables and eigenvalue table of the handle's GEMM engine
+  const void* Sx() const {
+    switch (prob.precision) {
+      case KKTDD_FP64: return Sx64;
+      case KKTDD_FP32: return Sx32;
+      default: return SxBF;
+    }
+  }
+  const void* Sy() const {
+    switch (prob.precision) {
+      case KKTDD_FP64: return Sy64;
+      case KKTDD_FP32: return Sy32;
+      default: return SyBF;
+    }
+  }
+  const void* invlam() const {
+    return prob.precision == KKTDD_FP64 ? (const void*)invlam64 : (const void*)invlam32;
+  }
+};
+

@@ -14,6 +14,9 @@ together by kkt_solve_batched as the bench solves them; whole-field parity of th
 operators, and every solution's residual recomputed by the oracle.
 """
 
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -21,6 +24,7 @@ from oracle.problem import Problem, subdomain_nodes, owned_nodes
 from oracle import operators as op
 from oracle import precond as pc
 from paper_2305_04421_amd import workloads as wl
+from common import relerr, relerr_blocks, relerr_blocks_2norm
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -30,9 +34,6 @@ torch = pytest.importorskip("torch")
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64).reshape(-1)).cuda()
 
-
-def relerr(a, b):
-    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
 @pytest.fixture(autouse=True)
@@ -58,19 +59,26 @@ def test_grid256_rhs_matvec_precond_whole_field():
         y = S.apply(dev(r)).cpu().numpy().reshape(shape)
         z = S.precond(dev(r)).cpu().numpy().reshape(shape)
     assert relerr(y, op.apply_K(p, r)) <= 1e-13
-    assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-11
+    assert relerr_blocks(z, pc.apply_Pinv(p, r)) <= 1e-11
 
 
-def test_grid256_solve_residual_by_oracle():
+# Inner precisions of the mixed solves the bench reports, with the iterations each may add to
+# the float64 count (float64 FGMRES acts as iterative refinement around them).
+MIXED_EXTRA = {"fp64": 0, "fp32": 2, "bf16x6": 2}
+
+
+@pytest.mark.parametrize("precision", list(MIXED_EXTRA))
+def test_grid256_solve_residual_by_oracle(precision):
     from paper_2305_04421_amd import KKTSolver
     params, recipe = wl.config("grid256")
     p = Problem(**params).validate()
     shape = (3,) + p.field_shape
     u0, ut = wl.data(params, recipe)
     f = op.rhs(p, u0, ut)
-    with KKTSolver(params) as S:
+    with KKTSolver(params, precision) as S:
         x, st = S.solve(dev(f), restart=30, maxit=300, rtol=1e-8)
     assert st["status"] == 0, st
+    assert st["iters"] <= GRID256_FP64_ITERS + MIXED_EXTRA[precision], st
     xs = x.cpu().numpy().reshape(shape)
     res = np.linalg.norm(f - op.apply_K(p, xs)) / np.linalg.norm(f)
     assert res <= 1e-8
@@ -79,9 +87,85 @@ def test_grid256_solve_residual_by_oracle():
     assert abs(res - st["relres_true"]) <= 1e-4 * res
 
 
+# float64 FGMRES(30) iterations of grid256 (equal to the oracle's on its first three steps,
+# tested below; the full oracle solve takes hours on a CPU)
+GRID256_FP64_ITERS = 32
+
+# ---- oracle results at full size (tests/golden/make_oracle_golden.py) ----------------------
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def golden(name):
+    with open(os.path.join(GOLDEN, f"oracle_fgmres_{name}.json")) as fh:
+        return json.load(fh)
+
+
+def sampled_block_errors(x, shape, blocks):
+    """Per KKT block: the largest sampled |x - oracle| over the block's largest oracle
+    magnitude, and the relative difference of the 2-norms."""
+    xv = x.view(shape[0], -1)
+    out = []
+    for b, ref in enumerate(blocks):
+        idx = torch.tensor(ref["index"], dtype=torch.long, device=x.device)
+        got = xv[b].index_select(0, idx).cpu().numpy()
+        d = float(np.abs(got - np.asarray(ref["value"])).max()) / ref["absmax"]
+        n = abs(float(xv[b].norm()) - ref["norm"]) / ref["norm"]
+        out.append((d, n))
+    return out
+
+
+@pytest.mark.parametrize("name", ["grid128", "grid128_w4", "grid256"])
+def test_three_step_iterates_equal_oracle(name):
+    """The FGMRES(30) iterate after exactly three Arnoldi steps, block by block (the Schur block
+    w carries the sweeps, sine-transform GEMMs and coarse level of every step)."""
+    from paper_2305_04421_amd import KKTSolver
+    params, recipe = wl.config(name)
+    g = golden(name)["three"]
+    p = Problem(**params).validate()
+    u0, ut = wl.data(params, recipe)
+    with KKTSolver(params) as S:
+        f = S.rhs(dev(u0), dev(ut))
+        x, st = S.solve(f, restart=30, maxit=3, rtol=1e-15)
+        errs = sampled_block_errors(x, (3,) + p.field_shape, g["blocks"])
+    assert st["status"] == 1 and st["iters"] == g["iterations"] == 3
+    for b, (d, n) in enumerate(errs):
+        assert d <= 1e-10 and n <= 1e-10, (name, b, errs)
+
+
+def test_grid128_pair_iterations_and_solutions_equal_oracle():
+    """The bench's grid128 step (both omegas solved as one batch, FGMRES(30) to 1e-8): the
+    iteration counts, the residual histories and the solutions equal the oracle's."""
+    from paper_2305_04421_amd import KKTSolver, solve_batched
+    names = ("grid128", "grid128_w4")
+    solvers, fs, shapes = [], [], []
+    try:
+        for name in names:
+            params, recipe = wl.config(name)
+            p = Problem(**params).validate()
+            u0, ut = wl.data(params, recipe)
+            S = KKTSolver(params)
+            solvers.append(S)
+            fs.append(S.rhs(dev(u0), dev(ut)))
+            shapes.append((3,) + p.field_shape)
+        xs, sts = solve_batched(solvers, fs, restart=30, maxit=600, rtol=1e-8)
+        for name, S, x, st, shape in zip(names, solvers, xs, sts, shapes):
+            g = golden(name)["converged"]
+            assert st["status"] == 0 and st["iters"] == g["iterations"], (name, st["iters"], g["iterations"])
+            assert st["relres_true"] <= 1e-8
+            hist = S.residual_history()
+            assert np.allclose(hist, g["history"], rtol=1e-6, atol=0.0), name
+            errs = sampled_block_errors(x, shape, g["blocks"])
+            for b, (d, n) in enumerate(errs):
+                assert d <= 1e-9 and n <= 1e-9, (name, b, errs)
+    finally:
+        for S in solvers:
+            S.close()
+
+
 # ---- grid128 pair and the uneven batch, solved as one batch -----------------------------------
 
-def _batched_residuals(cases, restart):
+def _batched_residuals(cases, restart, precision="fp64"):
     """Solve every (params, recipe) case in one kkt_solve_batched call to 1e-8; return the
     oracle's relative residual of each solution and the library's stats."""
     from paper_2305_04421_amd import KKTSolver, solve_batched
@@ -91,7 +175,7 @@ def _batched_residuals(cases, restart):
             p = Problem(**params).validate()
             u0, ut = wl.data(params, recipe)
             f = op.rhs(p, u0, ut)
-            S = KKTSolver(params)
+            S = KKTSolver(params, precision)
             solvers.append(S)
             fs.append(S.rhs(dev(u0), dev(ut)))
             fh.append((p, f))
@@ -120,7 +204,7 @@ def test_grid128_pair_operators_whole_field():
             z = S.precond(dev(r)).cpu().numpy().reshape(shape)
         assert relerr(fd, op.rhs(p, u0, ut)) <= 1e-13, name
         assert relerr(y, op.apply_K(p, r)) <= 1e-13, name
-        assert relerr(z, pc.apply_Pinv(p, r)) <= 1e-11, name
+        assert relerr_blocks(z, pc.apply_Pinv(p, r)) <= 1e-11, name
 
 
 def test_grid128_pair_batched_solve_residuals():
@@ -131,9 +215,10 @@ def test_grid128_pair_batched_solve_residuals():
         assert abs(res - st["relres_true"]) <= 1e-4 * res
 
 
-def test_uneven_batch_solve_residuals():
+@pytest.mark.parametrize("precision", ["fp64", "auto"])
+def test_uneven_batch_solve_residuals(precision):
     cases = list(wl.batch_uneven(64, seed=4))
-    results = _batched_residuals(cases, restart=12)
+    results = _batched_residuals(cases, restart=12, precision=precision)
     assert len(results) == 64
     for res, st in results:
         assert st["status"] == 0, st
@@ -144,6 +229,8 @@ def test_uneven_batch_solve_residuals():
 # ---- grid512: sampled outputs ------------------------------------------------------------
 
 NODES_512 = (1, 2, 1023, 1024, 2047, 2048)
+# float64 FGMRES(12) iterations of grid512 (the oracle cannot solve it whole on a CPU)
+GRID512_FP64_ITERS = 33
 
 
 def window(params, p, count):
@@ -211,7 +298,15 @@ def separable_field(p, seed, device=None):
             B[:, :, None, None] * Y2[None, None, :, None] * X2)
 
 
-def test_grid512_one_level_sweeps_of_sampled_subdomains():
+# Bound of the sampled one-level sweeps per inner precision: float64 as every preconditioner
+# test; float32 and split bfloat16 (float32-equivalent operands, float32 accumulation) leave
+# about 1e-7 relative rounding per transform, amplified by kappa(D_sigma) = 968 and chained over
+# 40 sweep steps.
+SWEEP_TOL = {"fp64": 1e-11, "fp32": 1e-3, "bf16x6": 1e-3}
+
+
+@pytest.mark.parametrize("precision", list(SWEEP_TOL))
+def test_grid512_one_level_sweeps_of_sampled_subdomains(precision):
     from paper_2305_04421_amd import KKTSolver
     params, _ = wl.config("grid512")
     params = dict(params, coarse=0)   # the sweeps alone: every subdomain is independent
@@ -220,7 +315,7 @@ def test_grid512_one_level_sweeps_of_sampled_subdomains():
     host_r = separable_field(p, 12)
     subs = (1, 64, p.n_sub)
     owned = sorted(n for s in subs for n in owned_nodes(p, s))
-    with KKTSolver(params) as S:
+    with KKTSolver(params, precision) as S:
         rd = separable_field(p, 12, "cuda").contiguous().view(-1)
         # the device and host constructions agree bit for bit on sampled nodes
         chk = slices(rd, shape, (1, p.nt))
@@ -238,12 +333,13 @@ def test_grid512_one_level_sweeps_of_sampled_subdomains():
         x = pc.adjoint_sweep(p, {n: p.h * y[n] for n in nodes}, nodes)
         for n in owned_nodes(p, s):
             rn = host_r([n])[:, 0]
-            assert relerr(zs[n][2], x[n]) <= 1e-11, (s, n)
+            assert relerr(zs[n][2], x[n]) <= SWEEP_TOL[precision], (s, n, relerr(zs[n][2], x[n]))
             assert relerr(zs[n][0], rn[0] / p.h) <= 1e-15
             assert relerr(zs[n][1], rn[1] / (p.omega * p.h)) <= 1e-15
 
 
-def test_grid512_solve_residual_rows():
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_grid512_solve_residual_rows(precision):
     from paper_2305_04421_amd import KKTSolver
     params, recipe = wl.config("grid512")
     p = Problem(**params).validate()
@@ -251,12 +347,13 @@ def test_grid512_solve_residual_rows():
     u0, ut = wl.data(params, recipe)
     fnorm = np.sqrt((p.h ** 2) * np.sum(ut * ut) + np.sum(u0 * u0))
     want_nodes = sorted({m for n in NODES_512 for m in (n - 1, n, n + 1) if 1 <= m <= p.nt})
-    with KKTSolver(params) as S:
+    with KKTSolver(params, precision) as S:
         fd = S.rhs(dev(u0), dev(ut))
         x, st = S.solve(fd, restart=12, maxit=300, rtol=1e-8)
         xs = slices(x, shape, want_nodes)
         del fd, x
     assert st["status"] == 0 and st["relres_true"] <= 1e-8, st
+    assert st["iters"] <= GRID512_FP64_ITERS + MIXED_EXTRA[precision], st
     for n in NODES_512:
         rn = rhs_rows_at(p, u0, ut, n) - window_rows(params, p, xs, n)
         # each node's share of the residual is bounded by the whole residual

@@ -560,6 +560,25 @@ def test_gmres_restarts_and_history_are_consistent():
     assert np.abs(res.x - xd).max() <= 1e-6 * np.abs(xd).max()
 
 
+def test_gmres_resumed_at_a_cycle_boundary_equals_one_solve():
+    """Restarted GMRES keeps no state across cycles but x: stopping after whole cycles and
+    starting again from the iterate gives the same iterate and the same step count as one
+    uninterrupted solve (the restart-boundary resume of a long solve)."""
+    p = _tiny(nt=8, n_sub=4, overlap=1, coarse=0)
+    rng = np.random.default_rng(19)
+    f = op.rhs(p, rng.standard_normal(p.slice_shape), rng.standard_normal(p.field_shape))
+    A = lambda v: op.apply_K(p, v)  # noqa: E731
+    M = lambda v: pc.apply_Pinv(p, v)  # noqa: E731
+    whole = gm.gmres(A, M, f, restart=3, maxit=300, rtol=1e-10)
+    assert whole.converged and whole.iterations > 6
+    first = gm.gmres(A, M, f, restart=3, maxit=6, rtol=1e-10)
+    assert not first.converged and first.iterations == 6
+    rest = gm.gmres(A, M, f, x0=first.x, restart=3, maxit=300, rtol=1e-10)
+    assert rest.converged and first.iterations + rest.iterations == whole.iterations
+    assert np.array_equal(rest.x, whole.x)
+    assert first.history + rest.history == whole.history
+
+
 def test_gmres_zero_rhs_and_maxit():
     p = _tiny()
     f = np.zeros((3,) + p.field_shape)
