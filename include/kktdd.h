@@ -187,6 +187,19 @@ int precond_apply(kktdd_handle* h, const double* r, double* z);
  * handle's precision.  b, x: nslices*(ny-1)*(nx-1) doubles; may alias. */
 int kkt_spatial_solve(kktdd_handle* h, const double* b, double* x, int32_t nslices, double shift);
 
+/* Allocation-free variant of kkt_spatial_solve, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid hipMalloc).  Same
+ * operation, arguments and results as kkt_spatial_solve (bitwise), but its eigenvalue table and
+ * work slices live in a fixed 64 MiB device array that the library holds per device until the
+ * process ends (its address is resolved by kkt_create), it calls no hipMalloc or hipFree, and
+ * it returns once the work is enqueued on the handle's stream (no synchronisation).
+ * Limit: one padded eigenvalue table plus 2*nslices padded slices in the handle's sweep
+ * element type (8 bytes for KKTDD_FP64, else 4) must fit 64 MiB; larger calls return
+ * KKTDD_EINVAL with the limit in kkt_last_error.  All calls on one device share the array:
+ * calls that overlap in time on one device (other streams or threads) race. */
+int kkt_spatial_solve_noalloc(kktdd_handle* h, const double* b, double* x, int32_t nslices,
+                              double shift);
+
 /* Solve K x = f by flexible GMRES(restart) right-preconditioned with P (Sec. 4).  x holds the
  * initial guess on entry and the iterate on exit.  Stops at the first Arnoldi step whose
  * rotated residual estimate is <= rtol*||f||, confirmed by the true residual (a new cycle

@@ -32,7 +32,7 @@ MAX_RESTART = 1024
 
 EXPORTED = ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_destroy", "kkt_size", "kkt_precision",
             "kkt_kappa", "kkt_tune_set", "kkt_tune_get", "kkt_rhs",
-            "kkt_apply", "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
+            "kkt_apply", "precond_apply", "kkt_spatial_solve", "kkt_spatial_solve_noalloc", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
             "kkt_profile_read", "kkt_residual_history", "kkt_last_error")
 
 # enum kktdd_kernel_class
@@ -93,6 +93,7 @@ def load():
     lib.kkt_apply.argtypes = [vp, vp, vp]
     lib.precond_apply.argtypes = [vp, vp, vp]
     lib.kkt_spatial_solve.argtypes = [vp, vp, vp, i32, dbl]
+    lib.kkt_spatial_solve_noalloc.argtypes = [vp, vp, vp, i32, dbl]
     lib.fgmres_solve.argtypes = [vp, vp, vp, i32, i32, dbl, ctypes.POINTER(Stats)]
     lib.kkt_solve_batched.argtypes = [i32, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       i32, i32, dbl, ctypes.POINTER(Stats)]
@@ -104,7 +105,7 @@ def load():
     lib.kkt_last_error.argtypes = []
     lib.kkt_last_error.restype = ctypes.c_char_p
     for name in ("kkt_validate", "kkt_memory_plan", "kkt_create", "kkt_tune_set", "kkt_tune_get", "kkt_rhs", "kkt_apply",
-                 "precond_apply", "kkt_spatial_solve", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
+                 "precond_apply", "kkt_spatial_solve", "kkt_spatial_solve_noalloc", "fgmres_solve", "kkt_solve_batched", "kkt_profile",
                  "kkt_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib

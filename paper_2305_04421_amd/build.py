@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkktdd.so")
-SOURCES = ["api.hip", "stencil.hip", "dst.hip", "coarse.hip", "krylov.hip", "modal.hip"]
+SOURCES = ["api.hip", "stencil.hip", "dst.hip", "coarse.hip", "krylov.hip", "modal.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

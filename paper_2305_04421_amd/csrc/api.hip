@@ -751,6 +751,11 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     delete H;
     return set_error(KKTDD_EHIP, "no HIP device");
   }
+  // the allocation-free entry point's scratch array: its address on this device, once
+  if (int e = noalloc_setup(H->device)) {
+    delete H;
+    return e;
+  }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     (void)hipGetLastError();

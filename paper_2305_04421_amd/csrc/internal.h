@@ -194,6 +194,10 @@ int launch_dcgs_update(long long n, double* V, long long ldv, int j, const doubl
 int launch_sumsq_blocks(const Geom& g, const double* r, double* partials, int nblocks,
                         hipStream_t s);
 
+// ---- noalloc.hip: the allocation-free spatial solve ----------------------------------------
+// Resolve the device address of the library's scratch array on `device` (current).
+int noalloc_setup(int device);
+
 // ---- per-launch timer ------------------------------------------------------------------
 struct Prof {
   bool on = false;
