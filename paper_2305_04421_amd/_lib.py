@@ -87,8 +87,8 @@ def load():
     lib.kkt_precision.restype = ctypes.c_int
     lib.kkt_kappa.argtypes = [P]
     lib.kkt_kappa.restype = dbl
-    lib.kkt_tune_set.argtypes = [i32] * 6
-    lib.kkt_tune_get.argtypes = [i32] * 4 + [ctypes.POINTER(i32)] * 2
+    lib.kkt_tune_set.argtypes = [i32] * 7
+    lib.kkt_tune_get.argtypes = [i32] * 4 + [ctypes.POINTER(i32)] * 3
     lib.kkt_rhs.argtypes = [vp, vp, vp, vp]
     lib.kkt_apply.argtypes = [vp, vp, vp]
     lib.precond_apply.argtypes = [vp, vp, vp]

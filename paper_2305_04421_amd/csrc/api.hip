@@ -308,7 +308,7 @@ Plan plan(const Geom& g, int precision, int sweep, int R) {
   } else {
     p.sweeps = (2 * (size_t)g.nd * MM + (size_t)g.nd * g.L * MM) * el;
   }
-  if (needs_rprime(g, precision, sweep)) p.sweeps += (size_t)g.P * 8;
+  if (needs_rprime(g, precision, sweep)) p.sweeps += (size_t)g.P * el;
   if (g.nb > 0) {
     const int hb = 2 * g.nb - 1;
     p.coarse = (size_t)g.nc * MM * 8 * 2 + (size_t)g.nxy * g.nc * (hb + 1) * 8;
@@ -530,7 +530,7 @@ int coarse_physical(kktdd_handle* H, const double* rw, const double* dscale, con
     c0 = H->c0;
   }
   *c0out = c0;
-  return launch_residual_prime(g, rw, dscale, c0, H->Dc0, H->DDc0, H->rprime, s);
+  return launch_residual_prime(g, rw, dscale, c0, H->Dc0, H->DDc0, H->rprime, H->elem == 4, s);
 }
 
 // Transform-hoisted Schur block (sine-mode space): see modal.hip.
@@ -543,7 +543,8 @@ int schur_apply_modal(kktdd_handle* H, const double* rw, const double* dscale, d
     // float32 transforms: coarse level and r' in float64 physical space, sweeps in mode space
     const double* c0 = nullptr;
     if (int e = coarse_physical(H, rw, dscale, &c0)) return e;
-    if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), H->rprime, nullptr, H->Mtmp, H->Rhat, g.nt, s)) return e;
+    if (int e = launch_dst_forward(g, prec, H->Sx(), H->Sy(), nullptr, nullptr, H->Mtmp, H->Rhat, g.nt, s,
+                                   static_cast<const float*>(H->rprime))) return e;
     if (int e = launch_modal_sweeps(g, prec, H->Rhat, nullptr, 0, H->lamx, H->lamy, H->Ysc, H->Mtmp,
                                     nullptr, s)) return e;
     return launch_dst_inverse(g, prec, H->Sx(), H->Sy(), H->Mtmp, H->Rhat, zw, g.nt, norm, c0, s);
@@ -600,7 +601,7 @@ int poison_workspace(kktdd_handle* H) {
   if (int e = fill(H->Tbuf, (size_t)g.nd * MM * el)) return e;
   if (int e = fill(H->Ubuf, (size_t)g.nd * MM * el)) return e;
   if (int e = fill(H->Ybuf, (size_t)g.nd * g.L * MM * el)) return e;
-  if (int e = fill(H->rprime, (size_t)g.P * 8)) return e;
+  if (int e = fill(H->rprime, (size_t)g.P * el)) return e;
   if (int e = fill(H->Rhat, (size_t)g.nt * MM * el)) return e;
   if (int e = fill(H->Mtmp, (size_t)g.nt * MM * el)) return e;
   if (int e = fill(H->Ysc, modal_store(g) * 8)) return e;
@@ -660,7 +661,10 @@ int autotune(kktdd_handle* H) {
   const size_t bytes = (size_t)nslices * MM * H->elem;
   KKT_HIP(hipMemsetAsync(a, 0, bytes, H->stream));
   KKT_HIP(hipMemsetAsync(b, 0, bytes, H->stream));
-  if (int e = launch_autotune(g, prec, H->Sx(), H->Sy(), H->invlam(), a, b, nslices, H->stream)) return e;
+  const bool step = H->prob.sweep == KKTDD_SWEEP_STEP;
+  if (step) KKT_HIP(hipMemsetAsync(H->rprime, 0, (size_t)g.P * H->elem, H->stream));
+  if (int e = launch_autotune(g, prec, H->Sx(), H->Sy(), H->invlam(), a, b, nslices, step ? H->rprime : nullptr,
+                              step ? H->Ybuf : nullptr, H->stream)) return e;
   KKT_HIP(hipStreamSynchronize(H->stream));
   return 0;
 }
@@ -751,11 +755,6 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     delete H;
     return set_error(KKTDD_EHIP, "no HIP device");
   }
-  // the allocation-free entry point's scratch array: its address on this device, once
-  if (int e = noalloc_setup(H->device)) {
-    delete H;
-    return e;
-  }
   size_t free_b = 0, total_b = 0;
   if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
     (void)hipGetLastError();
@@ -769,6 +768,12 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     char buf[160];
     std::snprintf(buf, sizeof buf, "problem needs %zu bytes, %zu free", pl.total(), free_b);
     return set_error(KKTDD_ENOMEM, buf);
+  }
+  // the allocation-free entry point's scratch array: its address on this device, once (after
+  // the memory check, so that a refused problem loads nothing onto the device)
+  if (int e = noalloc_setup(H->device)) {
+    delete H;
+    return e;
   }
   if (int e = build_tables(H)) return fail(e);
   const size_t MM = (size_t)g.padded();
@@ -790,8 +795,11 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
     H->Ubuf = u;
     H->Ybuf = y;
   }
-  if (needs_rprime(g, prob->precision, prob->sweep))
-    if (int e = dalloc(H, &H->rprime, (size_t)g.P)) return fail(e);
+  if (needs_rprime(g, prob->precision, prob->sweep)) {
+    unsigned char* rp = nullptr;
+    if (int e = dalloc(H, &rp, (size_t)g.P * el)) return fail(e);
+    H->rprime = rp;
+  }
   if (g.nb > 0) {
     if (physical_coarse(g, prob->precision, prob->sweep)) {
       if (int e = dalloc(H, &H->r0, (size_t)g.nc * g.nxy)) return fail(e);
@@ -841,13 +849,13 @@ size_t kkt_size(const kktdd_handle* H) { return H ? (size_t)(3 * H->g.P) : 0; }
 int kkt_precision(const kktdd_handle* H) { return H ? H->prob.precision : KKTDD_EINVAL; }
 
 int kkt_tune_set(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t waves,
-                 int32_t deep) {
-  return tune_set(kind, precision, extent, nslices, waves, deep);
+                 int32_t deep, int32_t width) {
+  return tune_set(kind, precision, extent, nslices, waves, deep, width);
 }
 
 int kkt_tune_get(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t* waves,
-                 int32_t* deep) {
-  return tune_get(kind, precision, extent, nslices, waves, deep);
+                 int32_t* deep, int32_t* width) {
+  return tune_get(kind, precision, extent, nslices, waves, deep, width);
 }
 
 double kkt_kappa(const kktdd_problem* prob) {

@@ -171,10 +171,11 @@ k_coarse_solve(Geom g, const double* __restrict__ fac, double* __restrict__ xhat
 // One thread per interior point and subdomain marches over the subdomain's owned nodes.  The
 // coarse slots of the subdomain (and the D c0 slots of its neighbours, needed at its first and
 // last node) are loaded once, so the per-node work is one load of r_w and one store.
+template <typename TO>
 __global__ void __launch_bounds__(kBlock)
 k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict__ dscale,
                  const double* __restrict__ c0, const double* __restrict__ Dc0,
-                 const double* __restrict__ DDc0, double* __restrict__ rp) {
+                 const double* __restrict__ DDc0, TO* __restrict__ rp) {
   const int pt = blockIdx.x * kBlock + threadIdx.x;
   const int s = blockIdx.y;
   if (pt >= g.nxy) return;
@@ -184,7 +185,7 @@ k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict
   if (!c0) {
     for (int n = n0; n <= n1; ++n) {
       const long long e = (long long)(n - 1) * nxy + pt;
-      rp[e] = sc * rw[e];
+      rp[e] = (TO)(sc * rw[e]);
     }
     return;
   }
@@ -211,7 +212,7 @@ k_residual_prime(Geom g, const double* __restrict__ rw, const double* __restrict
       Sc -= Dprev - (C0 + ph * C1);
     }
     const long long e = (long long)(n - 1) * nxy + pt;
-    rp[e] = sc * rw[e] - Sc * invh;
+    rp[e] = (TO)(sc * rw[e] - Sc * invh);
   }
 }
 
@@ -251,12 +252,17 @@ int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStrea
 
 int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
                           const double* c0, const double* Dc0, const double* DDc0,
-                          double* rprime, hipStream_t s) {
+                          void* rprime, int f32, hipStream_t s) {
   prof_begin(KKTDD_K_COARSE, s);
-  hipLaunchKernelGGL(k_residual_prime, dim3((g.nxy + kBlock - 1) / kBlock, g.nd), dim3(kBlock), 0,
-                     s, g, rw, dscale, c0, Dc0, DDc0, rprime);
+  const dim3 grid((g.nxy + kBlock - 1) / kBlock, g.nd);
+  if (f32)
+    hipLaunchKernelGGL(k_residual_prime<float>, grid, dim3(kBlock), 0, s, g, rw, dscale, c0, Dc0, DDc0,
+                       static_cast<float*>(rprime));
+  else
+    hipLaunchKernelGGL(k_residual_prime<double>, grid, dim3(kBlock), 0, s, g, rw, dscale, c0, Dc0, DDc0,
+                       static_cast<double*>(rprime));
   KKT_HIP(hipGetLastError());
-  prof_end(KKTDD_K_COARSE, s, 16.0 * g.P, 0.0);
+  prof_end(KKTDD_K_COARSE, s, (f32 ? 12.0 : 16.0) * g.P, 0.0);
   return 0;
 }
 

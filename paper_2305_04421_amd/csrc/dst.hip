@@ -84,33 +84,46 @@ constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefaul
 // ---- plain engines (f64, f32) ----------------------------------------------------------
 // A half-transform table Q holds two H x H blocks (H = M/2), block b at Q + b*H*H, its rows
 // stored in k-step groups (see the table loads below).
-// gemm_right: acc[t] += A(:, half blk) * Q[blk](:, tile),  A = 16 x M operand in LDS.
-// gemm_left:  acc[t] += Q[blk](:, tile)^T * B(half blk, :), B = M x 16 operand in LDS.
-// Output tile t of a wave is local tile lt0 + t*lts of half blk.
+// gemm_right: acc[w][t] += A_w(:, half blk) * Q[blk](:, tile), A_w = row block w (16 rows) of
+//             the 16W x M operand in LDS.
+// gemm_left:  acc[w][t] += Q[blk](:, tile)^T * B_w(half blk, :), B_w = column block w (16
+//             columns) of the M x 16W operand in LDS.
+// Output tile t of a wave is local tile lt0 + t*lts of half blk.  A wave loads each table
+// fragment once and uses it for all W blocks of the workgroup, so a workgroup of W blocks reads
+// the table W times less per row (or column) than W workgroups of one block; every output
+// element still sums over k in the same order, so W never changes a result.
 template <typename T>
 struct EngPlain {
   using data_t = T;
   using acc_t = typename AccT<T>::type;
   using s_t = T;
   static constexpr int kTableParts = 1;
-  static __host__ __device__ size_t rows_lds(int M) { return (size_t)16 * (M + 1) * sizeof(T); }
-  static __host__ __device__ size_t cols_lds(int M) { return (size_t)M * 17 * sizeof(T); }
+  template <int W> static __host__ __device__ size_t rows_lds(int M) { return (size_t)16 * W * (M + 1) * sizeof(T); }
+  template <int W> static __host__ __device__ size_t cols_lds(int M) { return (size_t)M * (16 * W + 1) * sizeof(T); }
   // The combine buffer of the inverse products is the operand buffer itself, in the same
   // layout, so a thread may overwrite the combine values it has just read.
   static constexpr bool kCombInPlace = true;
-  static __host__ __device__ size_t rows_lds_total(int M) { return rows_lds(M); }
-  static __host__ __device__ size_t cols_lds_total(int M) { return cols_lds(M); }
+  template <int W> static __host__ __device__ size_t rows_lds_total(int M) { return rows_lds<W>(M); }
+  template <int W> static __host__ __device__ size_t cols_lds_total(int M) { return cols_lds<W>(M); }
+  // Three or four tiles per wave with the default ring, one block (or two in float32): two
+  // 8-wave workgroups share a CU, their registers capped.
+  template <int TPW, int PD, int W>
+  static constexpr bool two_per_cu() {
+    return (TPW == 3 || TPW == 4) && PD == kPDDefault && (W == 1 || (W == 2 && sizeof(T) == 4));
+  }
   static __device__ int acc_row(int lk, int r) {
     if constexpr (sizeof(T) == 8) return lk + 4 * r; else return 4 * lk + r;
   }
-  // rows operand A[16][M+1]
+  // rows operand A[16W][M+1]
+  template <int W>
   static __device__ void put_a(unsigned char* lds, int M, int r, int c, T v) {
     reinterpret_cast<T*>(lds)[r * (M + 1) + c] = v;
   }
-  // cols operand B[M][17]
+  // cols operand B[M][16W+1]
+  template <int W>
   static __device__ void put_b(unsigned char* lds, int M, int k, int c, T v) {
     (void)M;
-    reinterpret_cast<T*>(lds)[k * 17 + c] = v;
+    reinterpret_cast<T*>(lds)[k * (16 * W + 1) + c] = v;
   }
   // Table loads: a wave-uniform base (block, k-step pair) plus a 32-bit per-lane offset per
   // tile.  The float64 tables store each block with k-steps interleaved in pairs: the element
@@ -118,10 +131,10 @@ struct EngPlain {
   // load brings a lane its operands of k-steps 2P and 2P + 1 (half the load instructions).
   // The float32 tables group four k-steps the same way (a quarter of the loads).
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_right2(const unsigned char* lds, const T* __restrict__ Q, int M,
-                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    const int H = M >> 1;
+                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    const int H = M >> 1, ldr = 16 * (M + 1);
     const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
     const T2* Qb = reinterpret_cast<const T2*>(Q + (long long)blk * H * H);
     int voff[TPW];
@@ -142,11 +155,20 @@ struct EngPlain {
       for (int p = 0; p < RP; ++p) {
         const int pr = pr0 + p;
         if (pr >= npr) break;
-        const T a0 = Ab[8 * pr], a1 = Ab[8 * pr + 4];
+        T a0[W], a1[W];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a0, bq[p][t].x, acc[t]);
+        for (int w = 0; w < W; ++w) {
+          a0[w] = Ab[w * ldr + 8 * pr];
+          a1[w] = Ab[w * ldr + 8 * pr + 4];
+        }
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a1, bq[p][t].y, acc[t]);
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a0[w], bq[p][t].x, acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a1[w], bq[p][t].y, acc[w][t]);
         const int kn = pr + RP;
         if (kn < npr) {
           const T2* Qk = Qb + (long long)(4 * kn) * H;
@@ -156,11 +178,11 @@ struct EngPlain {
       }
     }
   }
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_left2(const T* __restrict__ Q, const unsigned char* lds, int M,
-                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    const int H = M >> 1;
-    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    const int H = M >> 1, ldb = 16 * W + 1;
+    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * ldb + li;
     const T2* Qb = reinterpret_cast<const T2*>(Q + (long long)blk * H * H);
     int voff[TPW];
 #pragma unroll
@@ -180,11 +202,20 @@ struct EngPlain {
       for (int p = 0; p < RP; ++p) {
         const int pr = pr0 + p;
         if (pr >= npr) break;
-        const T b0 = Bb[8 * pr * 17], b1 = Bb[(8 * pr + 4) * 17];
+        T b0[W], b1[W];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].x, b0, acc[t]);
+        for (int w = 0; w < W; ++w) {
+          b0[w] = Bb[8 * pr * ldb + 16 * w];
+          b1[w] = Bb[(8 * pr + 4) * ldb + 16 * w];
+        }
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].y, b1, acc[t]);
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].x, b0[w], acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].y, b1[w], acc[w][t]);
         const int kn = pr + RP;
         if (kn < npr) {
           const T2* Qk = Qb + (long long)(4 * kn) * H;
@@ -195,10 +226,10 @@ struct EngPlain {
     }
   }
   // float32: k-steps in groups of four, one 16-byte load per lane brings four of them.
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_right4(const unsigned char* lds, const T* __restrict__ Q, int M,
-                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    const int H = M >> 1;
+                                     int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    const int H = M >> 1, ldr = 16 * (M + 1);
     const T* Ab = reinterpret_cast<const T*>(lds) + li * (M + 1) + blk * H + lk;
     const float4* Qb = reinterpret_cast<const float4*>(Q + (long long)blk * H * H);
     int voff[TPW];
@@ -219,15 +250,30 @@ struct EngPlain {
       for (int p = 0; p < RP; ++p) {
         const int gr = gr0 + p;
         if (gr >= ngr) break;
-        const T a0 = Ab[16 * gr], a1 = Ab[16 * gr + 4], a2 = Ab[16 * gr + 8], a3 = Ab[16 * gr + 12];
+        T a0[W], a1[W], a2[W], a3[W];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a0, bq[p][t].x, acc[t]);
+        for (int w = 0; w < W; ++w) {
+          a0[w] = Ab[w * ldr + 16 * gr];
+          a1[w] = Ab[w * ldr + 16 * gr + 4];
+          a2[w] = Ab[w * ldr + 16 * gr + 8];
+          a3[w] = Ab[w * ldr + 16 * gr + 12];
+        }
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a1, bq[p][t].y, acc[t]);
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a2, bq[p][t].z, acc[t]);
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a0[w], bq[p][t].x, acc[w][t]);
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(a3, bq[p][t].w, acc[t]);
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a1[w], bq[p][t].y, acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a2[w], bq[p][t].z, acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a3[w], bq[p][t].w, acc[w][t]);
         const int kn = gr + RP;
         if (kn < ngr) {
           const float4* Qk = Qb + (long long)(4 * kn) * H;
@@ -237,11 +283,11 @@ struct EngPlain {
       }
     }
   }
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_left4(const T* __restrict__ Q, const unsigned char* lds, int M,
-                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    const int H = M >> 1;
-    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * 17 + li;
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    const int H = M >> 1, ldb = 16 * W + 1;
+    const T* Bb = reinterpret_cast<const T*>(lds) + (blk * H + lk) * ldb + li;
     const float4* Qb = reinterpret_cast<const float4*>(Q + (long long)blk * H * H);
     int voff[TPW];
 #pragma unroll
@@ -261,16 +307,30 @@ struct EngPlain {
       for (int p = 0; p < RP; ++p) {
         const int gr = gr0 + p;
         if (gr >= ngr) break;
-        const T b0 = Bb[16 * gr * 17], b1 = Bb[(16 * gr + 4) * 17], b2 = Bb[(16 * gr + 8) * 17],
-                b3 = Bb[(16 * gr + 12) * 17];
+        T b0[W], b1[W], b2[W], b3[W];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].x, b0, acc[t]);
+        for (int w = 0; w < W; ++w) {
+          b0[w] = Bb[16 * gr * ldb + 16 * w];
+          b1[w] = Bb[(16 * gr + 4) * ldb + 16 * w];
+          b2[w] = Bb[(16 * gr + 8) * ldb + 16 * w];
+          b3[w] = Bb[(16 * gr + 12) * ldb + 16 * w];
+        }
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].y, b1, acc[t]);
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].z, b2, acc[t]);
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].x, b0[w], acc[w][t]);
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mfma16(aq[p][t].w, b3, acc[t]);
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].y, b1[w], acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].z, b2[w], acc[w][t]);
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+#pragma unroll
+          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].w, b3[w], acc[w][t]);
         const int kn = gr + RP;
         if (kn < ngr) {
           const float4* Qk = Qb + (long long)(4 * kn) * H;
@@ -282,24 +342,25 @@ struct EngPlain {
   }
   // Table operand groups: kGroup k-steps per load (two in float64, four in float32).
   static constexpr int kGroup = sizeof(T) == 8 ? 2 : 4;
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_right(const unsigned char* lds, const T* __restrict__ Q, int M,
-                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    if constexpr (sizeof(T) == 8) gemm_right2<TPW, kPD>(lds, Q, M, blk, lt0, lts, li, lk, acc);
-    else gemm_right4<TPW, kPD>(lds, Q, M, blk, lt0, lts, li, lk, acc);
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    if constexpr (sizeof(T) == 8) gemm_right2<TPW, kPD, W>(lds, Q, M, blk, lt0, lts, li, lk, acc);
+    else gemm_right4<TPW, kPD, W>(lds, Q, M, blk, lt0, lts, li, lk, acc);
   }
-  template <int TPW, int kPD>
+  template <int TPW, int kPD, int W>
   static __device__ void gemm_left(const T* __restrict__ Q, const unsigned char* lds, int M,
-                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    if constexpr (sizeof(T) == 8) gemm_left2<TPW, kPD>(Q, lds, M, blk, lt0, lts, li, lk, acc);
-    else gemm_left4<TPW, kPD>(Q, lds, M, blk, lt0, lts, li, lk, acc);
+                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    if constexpr (sizeof(T) == 8) gemm_left2<TPW, kPD, W>(Q, lds, M, blk, lt0, lts, li, lk, acc);
+    else gemm_left4<TPW, kPD, W>(Q, lds, M, blk, lt0, lts, li, lk, acc);
   }
 };
 
 // ---- split-bfloat16 engines -------------------------------------------------------------
 // Tables hold three bfloat16 parts, part p at offset p*M*M/2 (two H x H blocks each).  Here
 // gemm_right reads Q[blk](tile, :) and gemm_left Q[blk](tile, :) as well (k contiguous, 16
-// bytes per lane), so these engines take the transposes of the plain engines' tables.
+// bytes per lane), so these engines take the transposes of the plain engines' tables.  The
+// W row (or column) blocks of a workgroup share each table fragment as in the plain engines.
 template <int SPLIT>
 struct EngBF {
   static constexpr int NP = SPLIT == 1 ? 1 : (SPLIT == 3 ? 2 : 3);   // parts per operand
@@ -307,18 +368,22 @@ struct EngBF {
   using acc_t = v4f;
   using s_t = __bf16;
   static constexpr int kTableParts = 3;
-  static __host__ __device__ size_t rows_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
-  static __host__ __device__ size_t cols_lds(int M) { return (size_t)NP * 16 * (M + 8) * 2; }
-  // The float combine buffers ([16][M+1] rows, [M][17] cols) overlap the operand parts, so
+  template <int W> static __host__ __device__ size_t rows_lds(int M) { return (size_t)NP * 16 * W * (M + 8) * 2; }
+  template <int W> static __host__ __device__ size_t cols_lds(int M) { return (size_t)NP * 16 * W * (M + 8) * 2; }
+  // The float combine buffers ([16W][M+1] rows, [M][16W+1] cols) overlap the operand parts, so
   // every combine value is read before the operand is written again.
   static constexpr bool kCombInPlace = false;
-  static __host__ __device__ size_t rows_lds_total(int M) {
-    const size_t c = (size_t)16 * (M + 1) * 4;
-    return rows_lds(M) > c ? rows_lds(M) : c;
+  template <int W> static __host__ __device__ size_t rows_lds_total(int M) {
+    const size_t c = (size_t)16 * W * (M + 1) * 4;
+    return rows_lds<W>(M) > c ? rows_lds<W>(M) : c;
   }
-  static __host__ __device__ size_t cols_lds_total(int M) {
-    const size_t c = (size_t)M * 17 * 4;
-    return cols_lds(M) > c ? cols_lds(M) : c;
+  template <int W> static __host__ __device__ size_t cols_lds_total(int M) {
+    const size_t c = (size_t)M * (16 * W + 1) * 4;
+    return cols_lds<W>(M) > c ? cols_lds<W>(M) : c;
+  }
+  template <int TPW, int PD, int W>
+  static constexpr bool two_per_cu() {
+    return (TPW == 3 || TPW == 4) && PD == kPDDefault && (W == 1 || (W == 2 && NP <= 2));
   }
   static __device__ int acc_row(int lk, int r) { return 4 * lk + r; }
   static __device__ void split(float v, __bf16 (&part)[NP]) {
@@ -329,35 +394,41 @@ struct EngBF {
       if constexpr (NP > 2) part[2] = (__bf16)(r1 - (float)part[1]);
     }
   }
-  // rows operand: NP arrays A_p[16][M+8] (k contiguous)
+  // rows operand: NP arrays A_p[16W][M+8] (k contiguous)
+  template <int W>
   static __device__ void put_a(unsigned char* lds, int M, int r, int c, float v) {
     __bf16 part[NP];
     split(v, part);
     __bf16* A = reinterpret_cast<__bf16*>(lds);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) A[(p * 16 + r) * (M + 8) + c] = part[p];
+    for (int p = 0; p < NP; ++p) A[(p * 16 * W + r) * (M + 8) + c] = part[p];
   }
-  // cols operand stored transposed: NP arrays Bt_p[16][M+8], Bt_p[c][k] = part_p(B[k][c])
+  // cols operand stored transposed: NP arrays Bt_p[16W][M+8], Bt_p[c][k] = part_p(B[k][c])
+  template <int W>
   static __device__ void put_b(unsigned char* lds, int M, int k, int c, float v) {
     __bf16 part[NP];
     split(v, part);
     __bf16* B = reinterpret_cast<__bf16*>(lds);
 #pragma unroll
-    for (int p = 0; p < NP; ++p) B[(p * 16 + c) * (M + 8) + k] = part[p];
+    for (int p = 0; p < NP; ++p) B[(p * 16 * W + c) * (M + 8) + k] = part[p];
   }
-  static __device__ v4f mma(const bf16x8 (&a)[NP], const bf16x8 (&b)[NP], v4f acc) {
-    if constexpr (SPLIT == 6) {
-      acc = mfma_bf(a[2], b[0], acc);
-      acc = mfma_bf(a[1], b[1], acc);
-      acc = mfma_bf(a[0], b[2], acc);
-    }
-    if constexpr (SPLIT >= 3) {
-      acc = mfma_bf(a[1], b[0], acc);
-      acc = mfma_bf(a[0], b[1], acc);
-    }
-    return mfma_bf(a[0], b[0], acc);
+  // Part products of one product, in the order every accumulator receives them (smallest
+  // first): a2b0, a1b1, a0b2 (x6), a1b0, a0b1 (x3, x6), a0b0.  The GEMM loops issue part
+  // product q for all of a wave's accumulators before part product q+1, so consecutive MFMAs
+  // never depend on each other; each accumulator still sums its part products in this order.
+  static constexpr int kProducts = SPLIT;
+  static __host__ __device__ constexpr int part_a(int q) {
+    return SPLIT == 6 ? (q == 0 ? 2 : q == 1 ? 1 : q == 2 ? 0 : q == 3 ? 1 : 0)
+                      : SPLIT == 3 ? (q == 0 ? 1 : 0) : 0;
   }
-  static constexpr int ring(int TPW) { return TPW * NP <= 8 ? 2 : 1; }
+  static __host__ __device__ constexpr int part_b(int q) {
+    return SPLIT == 6 ? (q == 0 ? 0 : q == 1 ? 1 : q == 2 ? 2 : q == 3 ? 0 : q == 4 ? 1 : 0)
+                      : SPLIT == 3 ? (q == 1 ? 1 : 0) : 0;
+  }
+  // table fragments kept in flight per tile and part: two k-steps while the ring fits the
+  // register budget of the launch shape, else one
+  template <int TPW, int W>
+  static constexpr int ring() { return TPW * NP <= (W == 1 ? 8 : 12) ? 2 : 1; }
   // fragment of local tile lt at k-step ks: Q_p[blk][lt*16 + li][32ks + 8lk .. +8], as a
   // wave-uniform base (part, block, k-step) plus a 32-bit per-lane offset
   static __device__ bf16x8 qload(const __bf16* __restrict__ Q, int M, int blk, int lt, int ks,
@@ -366,10 +437,10 @@ struct EngBF {
     const __bf16* base = Q + (long long)p * M * H + (long long)blk * H * H + 32 * ks;
     return *reinterpret_cast<const bf16x8*>(base + ((lt * 16 + li) * H + 8 * lk));
   }
-  template <int TPW, int PD_unused>
+  template <int TPW, int PD_unused, int W>
   static __device__ void gemm_right(const unsigned char* lds, const __bf16* __restrict__ Q, int M,
-                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    constexpr int RD = ring(TPW);
+                                    int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    constexpr int RD = ring<TPW, W>();
     const int H = M >> 1, lda = M + 8;
     const __bf16* A = reinterpret_cast<const __bf16*>(lds) + blk * H + 8 * lk;
     bf16x8 bq[RD][TPW][NP];
@@ -385,12 +456,19 @@ struct EngBF {
       for (int d = 0; d < RD; ++d) {
         const int ks = ks0 + d;
         if (ks >= nks) break;
-        bf16x8 af[NP];
+        bf16x8 af[W][NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          af[p] = *reinterpret_cast<const bf16x8*>(A + (p * 16 + li) * lda + 32 * ks);
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mma(af, bq[d][t], acc[t]);
+          for (int p = 0; p < NP; ++p)
+            af[w][p] = *reinterpret_cast<const bf16x8*>(A + (p * 16 * W + w * 16 + li) * lda + 32 * ks);
+#pragma unroll
+        for (int q = 0; q < kProducts; ++q)
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+              acc[w][t] = mfma_bf(af[w][part_a(q)], bq[d][t][part_b(q)], acc[w][t]);
         const int kn = ks + RD;
         if (kn < nks) {
 #pragma unroll
@@ -401,10 +479,10 @@ struct EngBF {
       }
     }
   }
-  template <int TPW, int PD_unused>
+  template <int TPW, int PD_unused, int W>
   static __device__ void gemm_left(const __bf16* __restrict__ Q, const unsigned char* lds, int M,
-                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[TPW]) {
-    constexpr int RD = ring(TPW);
+                                   int blk, int lt0, int lts, int li, int lk, acc_t (&acc)[W][TPW]) {
+    constexpr int RD = ring<TPW, W>();
     const int H = M >> 1, ldb = M + 8;
     const __bf16* Bt = reinterpret_cast<const __bf16*>(lds) + blk * H + 8 * lk;
     bf16x8 aq[RD][TPW][NP];
@@ -420,12 +498,19 @@ struct EngBF {
       for (int d = 0; d < RD; ++d) {
         const int ks = ks0 + d;
         if (ks >= nks) break;
-        bf16x8 bf[NP];
+        bf16x8 bf[W][NP];
 #pragma unroll
-        for (int p = 0; p < NP; ++p)
-          bf[p] = *reinterpret_cast<const bf16x8*>(Bt + (p * 16 + li) * ldb + 32 * ks);
+        for (int w = 0; w < W; ++w)
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) acc[t] = mma(aq[d][t], bf, acc[t]);
+          for (int p = 0; p < NP; ++p)
+            bf[w][p] = *reinterpret_cast<const bf16x8*>(Bt + (p * 16 * W + w * 16 + li) * ldb + 32 * ks);
+#pragma unroll
+        for (int q = 0; q < kProducts; ++q)
+#pragma unroll
+          for (int w = 0; w < W; ++w)
+#pragma unroll
+            for (int t = 0; t < TPW; ++t)
+              acc[w][t] = mfma_bf(aq[d][t][part_a(q)], bf[w][part_b(q)], acc[w][t]);
         const int kn = ks + RD;
         if (kn < nks) {
 #pragma unroll
@@ -439,10 +524,10 @@ struct EngBF {
 };
 
 // ---- row kernel ------------------------------------------------------------------------
-// One workgroup = 16 rows of one slice.  Optional GEMM1 (inverse product y = g1_scale * U S_x,
-// U in x-mode space) with its epilogue stores, then optional formation of b and GEMM2
-// (forward product T = b S_x, T in x-mode space).  Both products are folded: the workgroup
-// works on mirrored column pairs (c, mx-1-c), 2*TPW pairs per thread.
+// One workgroup = RB blocks of 16 rows of one slice.  Optional GEMM1 (inverse product
+// y = g1_scale * U S_x, U in x-mode space) with its epilogue stores, then optional formation of
+// b and GEMM2 (forward product T = b S_x, T in x-mode space).  Both products are folded: the
+// workgroup works on mirrored column pairs (c, mx-1-c), 2*TPW pairs per thread and row block.
 enum BMode { B_NONE = 0, B_RPRIME_PLUS_Y = 1, B_H_YBUF_PLUS_Y = 2, B_H_Y = 3, B_INPUT = 4 };
 enum OutMode { OUT_NONE = 0, OUT_OWNED = 1, OUT_PLAIN = 2 };
 
@@ -460,7 +545,8 @@ struct RowArgs {
   int g1_step;               // sweep step of the GEMM1 result (OUT_OWNED)
   int b_mode;
   int b_step;                // sweep step whose right-hand side is formed (B_RPRIME_PLUS_Y)
-  const double* rin;         // r' field (nt slices) or plain input slices (B_INPUT)
+  const double* rin;         // r' field (nt slices) or plain input slices (B_INPUT), float64
+  const float* rin32;        // the same in float32 (read instead of rin when set)
   const double* in_scale;    // device factor of the B_INPUT slices (nullptr: 1)
   const T* ybuf_in;          // padded (B_H_YBUF_PLUS_Y)
   long long ybuf_stride;
@@ -494,88 +580,115 @@ __device__ inline const typename Eng::s_t* table(const void* S, int M, int inver
          (inverse ? (long long)Eng::kTableParts * M * (M >> 1) : 0);
 }
 
-// Three or four tiles per wave with the default ring: registers are capped so that two
-// 8-wave workgroups share a CU (one's loads and stores overlap the other's MFMAs), and the
-// right-hand-side operands are fetched after the first product instead of before it.
-template <int TPW, int PD>
-constexpr bool rows_two_per_cu() { return (TPW == 3 || TPW == 4) && PD == kPDDefault; }
-
-template <typename Eng, int TPW, int PD>
-__global__ void __launch_bounds__(512, (rows_two_per_cu<TPW, PD>() ? 4 : 1))
+// Three or four tiles per wave with the default ring (and the block counts listed in each
+// engine's two_per_cu): registers are capped so that two 8-wave workgroups share a CU (one's
+// loads and stores overlap the other's MFMAs), and the right-hand-side operands are fetched
+// after the first product instead of before it.
+template <typename Eng, int TPW, int PD, int RB>
+__global__ void __launch_bounds__(512, (Eng::template two_per_cu<TPW, PD, RB>() ? 4 : 1))
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
+  constexpr bool kTwo = Eng::template two_per_cu<TPW, PD, RB>();
   extern __shared__ unsigned char smem_raw[];
   const int Mx = g.Mx, Hx = Mx >> 1, mx = g.mx, Ax = (mx + 1) / 2, ldc = Mx + 1;
-  int rb, s;
-  if (!tile_and_slice((g.my + 15) / 16, a.nsl, rb, s)) return;
+  int rg, s;
+  if (!tile_and_slice((g.my + 16 * RB - 1) / (16 * RB), a.nsl, rg, s)) return;
+  const int row0 = rg * 16 * RB;       // first row of the workgroup's RB row blocks
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
   T* comb = reinterpret_cast<T*>(smem_raw);
-  constexpr int NPR = 2 * TPW;   // 16 rows x Hx pairs = NPR * blockDim.x
-  acc_t acc[TPW];
+  constexpr int NPR = 2 * TPW;   // per row block: 16 rows x Hx pairs = NPR * blockDim.x
+  acc_t acc[RB][TPW];
 
   // node of a sweep step in this subdomain (0-based subdomain s): first = s*k + 1 - delta
   const int first = s * g.k + 1 - g.delta;
 
   // Right-hand-side operands of b at both points of every pair, fetched before GEMM1 so their
   // latency hides behind it (after it where registers are capped).
-  T pre[NPR][2];
+  T pre[RB][NPR][2];
   auto load_pre = [&]() {
     if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
       const int bnode = first + a.b_step;
       const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
 #pragma unroll
-      for (int i = 0; i < NPR; ++i) {
-        const int e = threadIdx.x + i * nthr;
-        const int r = e / Hx, k = e - r * Hx;
-        const int row = rb * 16 + r;
-        T v1 = 0, v2 = 0;
-        if (row < g.my && k < Ax) {
-          const int c2 = mx - 1 - k;
-          if (a.b_mode == B_RPRIME_PLUS_Y) {
-            if (bnode >= 1) {
-              const double* src = a.rin + (long long)(bnode - 1) * g.nxy + (long long)row * mx;
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) {
+          const int e = threadIdx.x + i * nthr;
+          const int r = e / Hx, k = e - r * Hx;
+          const int row = row0 + rr * 16 + r;
+          T v1 = 0, v2 = 0;
+          if (row < g.my && k < Ax) {
+            const int c2 = mx - 1 - k;
+            if (a.b_mode == B_RPRIME_PLUS_Y) {
+              if (bnode >= 1) {
+                const long long o = (long long)(bnode - 1) * g.nxy + (long long)row * mx;
+                if (a.rin32) {
+                  v1 = (T)a.rin32[o + k];
+                  v2 = (T)a.rin32[o + c2];
+                } else {
+                  v1 = (T)a.rin[o + k];
+                  v2 = (T)a.rin[o + c2];
+                }
+              }
+            } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
+              const T* src = a.ybuf_in + s * a.ybuf_stride + (long long)row * Mx;
+              v1 = src[k];
+              v2 = src[c2];
+            } else if (a.rin32) {   // float32 input, never scaled
+              const float* src = a.rin32 + (long long)s * g.nxy + (long long)row * mx;
               v1 = (T)src[k];
               v2 = (T)src[c2];
+            } else {
+              const double* src = a.rin + (long long)s * g.nxy + (long long)row * mx;
+              v1 = (T)(isc * src[k]);
+              v2 = (T)(isc * src[c2]);
             }
-          } else if (a.b_mode == B_H_YBUF_PLUS_Y) {
-            const T* src = a.ybuf_in + s * a.ybuf_stride + (long long)row * Mx;
-            v1 = src[k];
-            v2 = src[c2];
-          } else {
-            const double* src = a.rin + (long long)s * g.nxy + (long long)row * mx;
-            v1 = (T)(isc * src[k]);
-            v2 = (T)(isc * src[c2]);
           }
+          pre[rr][i][0] = v1;
+          pre[rr][i][1] = v2;
         }
-        pre[i][0] = v1;
-        pre[i][1] = v2;
-      }
     }
   };
-  if constexpr (!rows_two_per_cu<TPW, PD>()) load_pre();
+  if constexpr (!kTwo) load_pre();
 
   // ---- GEMM1: E | O = U(odd modes) F_odd^T | U(even modes) F_even^T, into the combine buffer
   if (a.g1_in) {
-    const T* src = a.g1_in + s * a.g1_stride + (long long)rb * 16 * Mx;
-    const int live_rows = g.my - rb * 16;   // rows at or past it are padding: read as zero
-    for (int e = threadIdx.x; e < 16 * Mx; e += nthr) {
+    // the workgroup's rows are one contiguous run of 16*RB*Mx elements; every thread issues
+    // all of its loads before the first LDS write, so they are in flight together
+    constexpr int NE = 4 * RB * TPW;   // elements per thread: 16*RB*Mx / blockDim.x
+    const T* src = a.g1_in + s * a.g1_stride + (long long)row0 * Mx;
+    const int live = (g.my - row0) * Mx;   // elements of live rows; rows past them read as zero
+    T buf[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      buf[j] = e < live ? src[e] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
       const int r = e / Mx;
-      Eng::put_a(smem_raw, Mx, r, e - r * Mx, r < live_rows ? src[e] : (T)0);
+      Eng::template put_a<RB>(smem_raw, Mx, r, e - r * Mx, buf[j]);
     }
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    Eng::template gemm_right<TPW, PD>(smem_raw, table<Eng>(a.Sx, Mx, 1), Mx, blk, lt0, lts, li, lk, acc);
+    for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) acc[rr][t] = acc_t{0, 0, 0, 0};
+    Eng::template gemm_right<TPW, PD, RB>(smem_raw, table<Eng>(a.Sx, Mx, 1), Mx, blk, lt0, lts, li, lk, acc);
     __syncthreads();  // every wave has read the operand, which the combine buffer overlays
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+    for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        comb[Eng::acc_row(lk, r) * ldc + blk * Hx + (lt0 + t * lts) * 16 + li] = (T)(acc[t][r] * a.g1_scale);
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          comb[(rr * 16 + Eng::acc_row(lk, r)) * ldc + blk * Hx + (lt0 + t * lts) * 16 + li] =
+              (T)(acc[rr][t][r] * a.g1_scale);
     __syncthreads();
   }
 
@@ -606,72 +719,84 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
       a.out64[(long long)(node - 1) * g.nxy + pt] = val;
     }
   };
-  T yv[NPR][2];
+  T yv[RB][NPR][2];
 #pragma unroll
-  for (int i = 0; i < NPR; ++i) {
-    const int e = threadIdx.x + i * nthr;
-    const int r = e / Hx, k = e - r * Hx;
-    const int row = rb * 16 + r;
-    const int c2 = mx - 1 - k;
-    T y1 = 0, y2 = 0;
-    if (a.g1_in) {
-      const T E = comb[r * ldc + k], O = comb[r * ldc + Hx + k];
-      y1 = E + O;
-      y2 = E - O;
-      if (k < Ax && row < g.my) {
-        store_y(row, k, y1);
-        if (k != c2) store_y(row, c2, y2);
+  for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = threadIdx.x + i * nthr;
+      const int r = e / Hx, k = e - r * Hx;
+      const int row = row0 + rr * 16 + r;
+      const int c2 = mx - 1 - k;
+      T y1 = 0, y2 = 0;
+      if (a.g1_in) {
+        const T* cr = comb + (rr * 16 + r) * ldc;
+        const T E = cr[k], O = cr[Hx + k];
+        y1 = E + O;
+        y2 = E - O;
+        if (k < Ax && row < g.my) {
+          store_y(row, k, y1);
+          if (k != c2) store_y(row, c2, y2);
+        }
       }
+      yv[rr][i][0] = y1;
+      yv[rr][i][1] = y2;
     }
-    yv[i][0] = y1;
-    yv[i][1] = y2;
-  }
   if (!form_b) return;
-  if constexpr (rows_two_per_cu<TPW, PD>()) load_pre();
+  if constexpr (kTwo) load_pre();
   if constexpr (!Eng::kCombInPlace) __syncthreads();   // combine values read before the operand is written
 #pragma unroll
-  for (int i = 0; i < NPR; ++i) {
-    const int e = threadIdx.x + i * nthr;
-    const int r = e / Hx, k = e - r * Hx;
-    const bool mid = k == mx - 1 - k;
-    const T y1 = yv[i][0], y2 = yv[i][1];
-    T b1 = 0, b2 = 0;
-    switch (a.b_mode) {
-      case B_RPRIME_PLUS_Y: b1 = pre[i][0] + y1; b2 = pre[i][1] + y2; break;
-      case B_H_YBUF_PLUS_Y: b1 = hT * pre[i][0] + y1; b2 = hT * pre[i][1] + y2; break;
-      case B_H_Y: b1 = hT * y1; b2 = hT * y2; break;
-      case B_INPUT: b1 = pre[i][0]; b2 = pre[i][1]; break;
+  for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+    for (int i = 0; i < NPR; ++i) {
+      const int e = threadIdx.x + i * nthr;
+      const int r = e / Hx, k = e - r * Hx;
+      const bool mid = k == mx - 1 - k;
+      const T y1 = yv[rr][i][0], y2 = yv[rr][i][1];
+      T b1 = 0, b2 = 0;
+      switch (a.b_mode) {
+        case B_RPRIME_PLUS_Y: b1 = pre[rr][i][0] + y1; b2 = pre[rr][i][1] + y2; break;
+        case B_H_YBUF_PLUS_Y: b1 = hT * pre[rr][i][0] + y1; b2 = hT * pre[rr][i][1] + y2; break;
+        case B_H_Y: b1 = hT * y1; b2 = hT * y2; break;
+        case B_INPUT: b1 = pre[rr][i][0]; b2 = pre[rr][i][1]; break;
+      }
+      T sum = 0, dif = 0;
+      if (k < Ax) {
+        sum = mid ? b1 : b1 + b2;
+        dif = mid ? (T)0 : b1 - b2;
+      }
+      Eng::template put_a<RB>(smem_raw, Mx, rr * 16 + r, k, sum);
+      Eng::template put_a<RB>(smem_raw, Mx, rr * 16 + r, Hx + k, dif);
     }
-    T sum = 0, dif = 0;
-    if (k < Ax) {
-      sum = mid ? b1 : b1 + b2;
-      dif = mid ? (T)0 : b1 - b2;
-    }
-    Eng::put_a(smem_raw, Mx, r, k, sum);
-    Eng::put_a(smem_raw, Mx, r, Hx + k, dif);
-  }
   __syncthreads();
 
   // ---- GEMM2: T = [sums | differences] (F_odd | F_even), stored in x-mode order -------------
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-  Eng::template gemm_right<TPW, PD>(smem_raw, table<Eng>(a.Sx, Mx, 0), Mx, blk, lt0, lts, li, lk, acc);
+  for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
-    const int col = blk * Hx + (lt0 + t * lts) * 16 + li;
+    for (int t = 0; t < TPW; ++t) acc[rr][t] = acc_t{0, 0, 0, 0};
+  Eng::template gemm_right<TPW, PD, RB>(smem_raw, table<Eng>(a.Sx, Mx, 0), Mx, blk, lt0, lts, li, lk, acc);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = rb * 16 + Eng::acc_row(lk, r);
-      a.g2_out[s * a.g2_stride + (long long)row * Mx + col] = (T)acc[t][r];
+  for (int rr = 0; rr < RB; ++rr) {
+    if (row0 + rr * 16 >= g.my) break;   // row blocks wholly past the interior write nothing
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const int col = blk * Hx + (lt0 + t * lts) * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + rr * 16 + Eng::acc_row(lk, r);
+        a.g2_out[s * a.g2_stride + (long long)row * Mx + col] = (T)acc[rr][t][r];
+      }
     }
   }
 }
 
 // ---- column kernel ---------------------------------------------------------------------
-// One workgroup = 16 columns of one slice.  fold: the input rows are points and the first
-// product is the forward transform X = S_y T (optionally ./ lambda); otherwise the input rows
-// are y-modes.  two: the inverse product U = S_y X follows, chained through LDS.  An inverse
-// last product writes point rows (mirrored pairs combined); a forward one writes mode rows.
+// One workgroup = CB blocks of 16 columns of one slice.  fold: the input rows are points and
+// the first product is the forward transform X = S_y T (optionally ./ lambda); otherwise the
+// input rows are y-modes.  two: the inverse product U = S_y X follows, chained through LDS.  An
+// inverse last product writes point rows (mirrored pairs combined); a forward one writes mode
+// rows.
 template <typename T>
 struct ColArgs {
   const void* Sy;      // engine's half-transform tables of y: forward, then inverse
@@ -685,91 +810,125 @@ struct ColArgs {
   int nsl = 0;         // set by the launcher: slice count of the slice-per-XCD grid, or 0
 };
 
-template <typename Eng, int TPW, int PD>
+template <typename Eng, int TPW, int PD, int CB>
 __global__ void __launch_bounds__(512)
 k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
   extern __shared__ unsigned char smem_raw[];
+  constexpr int NC = 16 * CB;       // columns of the workgroup
   const int Mx = g.Mx, My = g.My, Hy = My >> 1, my = g.my, Ay = (my + 1) / 2;
-  int cb, s;
-  if (!tile_and_slice(g.Mx / 16, a.nsl, cb, s)) return;
+  int cg, s;
+  if (!tile_and_slice(g.Mx / NC, a.nsl, cg, s)) return;
   const int nthr = blockDim.x, nw = nthr >> 6;
   const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lk = lane >> 4;
   const int blk = wave & 1, lt0 = wave >> 1, lts = nw >> 1;
   T* comb = reinterpret_cast<T*>(smem_raw);
 
-  const T* src = a.in + s * a.in_stride + cb * 16;
+  // Staging: every thread issues all of its loads before the first LDS write, so they are in
+  // flight together.  fold: Hy*NC (point, mirrored point) pairs; else My*NC mode values.
+  const T* src = a.in + s * a.in_stride + cg * NC;
   if (a.fold) {
-    for (int e = threadIdx.x; e < Hy * 16; e += nthr) {
-      const int k = e >> 4, c = e & 15;
+    constexpr int NE = 2 * TPW * CB;   // pairs per thread: Hy*NC / blockDim.x
+    T v1[NE], v2[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int k = e / NC, c = e % NC, r2 = my - 1 - k;
+      v1[j] = k < Ay ? src[(long long)k * Mx + c] : (T)0;
+      v2[j] = (k < Ay && r2 != k) ? src[(long long)r2 * Mx + c] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int k = e / NC, c = e % NC;
       T sum = 0, dif = 0;
       if (k < Ay) {
-        const int r2 = my - 1 - k;
-        const T v1 = src[(long long)k * Mx + c];
-        if (r2 == k) {
-          sum = v1;
+        if (my - 1 - k == k) {
+          sum = v1[j];
         } else {
-          const T v2 = src[(long long)r2 * Mx + c];
-          sum = v1 + v2;
-          dif = v1 - v2;
+          sum = v1[j] + v2[j];
+          dif = v1[j] - v2[j];
         }
       }
-      Eng::put_b(smem_raw, My, k, c, sum);
-      Eng::put_b(smem_raw, My, Hy + k, c, dif);
+      Eng::template put_b<CB>(smem_raw, My, k, c, sum);
+      Eng::template put_b<CB>(smem_raw, My, Hy + k, c, dif);
     }
   } else {
-    for (int e = threadIdx.x; e < My * 16; e += nthr)
-      Eng::put_b(smem_raw, My, e >> 4, e & 15, src[(long long)(e >> 4) * Mx + (e & 15)]);
+    constexpr int NE = 4 * TPW * CB;   // values per thread: My*NC / blockDim.x
+    T v[NE];
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      v[j] = src[(long long)(e / NC) * Mx + (e % NC)];
+    }
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      Eng::template put_b<CB>(smem_raw, My, e / NC, e % NC, v[j]);
+    }
   }
   __syncthreads();
 
-  acc_t acc[TPW];
+  acc_t acc[CB][TPW];
   auto product = [&](int inverse) {
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) acc[t] = acc_t{0, 0, 0, 0};
-    Eng::template gemm_left<TPW, PD>(table<Eng>(a.Sy, My, inverse), smem_raw, My, blk, lt0, lts, li, lk, acc);
+    for (int w = 0; w < CB; ++w)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) acc[w][t] = acc_t{0, 0, 0, 0};
+    Eng::template gemm_left<TPW, PD, CB>(table<Eng>(a.Sy, My, inverse), smem_raw, My, blk, lt0, lts, li, lk, acc);
   };
   product(!a.fold);
   if (a.invlam) {
-    const T* il = a.invlam + (long long)(blk * Hy + lt0 * 16) * Mx + cb * 16;
+    const T* il = a.invlam + (long long)(blk * Hy + lt0 * 16) * Mx + cg * NC;
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+    for (int w = 0; w < CB; ++w)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        acc[t][r] *= il[(t * lts * 16 + Eng::acc_row(lk, r)) * Mx + li];
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[w][t][r] *= il[(t * lts * 16 + Eng::acc_row(lk, r)) * Mx + w * 16 + li];
   }
   if (a.two) {
     __syncthreads();
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
+    for (int w = 0; w < CB; ++w)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        Eng::put_b(smem_raw, My, blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r), li, (T)acc[t][r]);
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          Eng::template put_b<CB>(smem_raw, My, blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r),
+                                  w * 16 + li, (T)acc[w][t][r]);
     __syncthreads();
     product(1);
   }
-  T* dst = a.out + s * a.out_stride + cb * 16;
+  T* dst = a.out + s * a.out_stride + cg * NC;
   if (a.fold && !a.two) {   // forward only: y-mode rows
+#pragma unroll
+    for (int w = 0; w < CB; ++w)
+#pragma unroll
+      for (int t = 0; t < TPW; ++t)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          dst[(long long)(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * Mx + w * 16 + li] =
+              (T)acc[w][t][r];
+    return;
+  }
+  // inverse last: E (odd modes) and O (even modes) of each pair through LDS, then the points
+  constexpr int ldc = NC + 1;
+  __syncthreads();  // every wave has read the operand, which the combine buffer overlays
+#pragma unroll
+  for (int w = 0; w < CB; ++w)
 #pragma unroll
     for (int t = 0; t < TPW; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        dst[(long long)(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * Mx + li] = (T)acc[t][r];
-    return;
-  }
-  // inverse last: E (odd modes) and O (even modes) of each pair through LDS, then the points
-  __syncthreads();  // every wave has read the operand, which the combine buffer overlays
-#pragma unroll
-  for (int t = 0; t < TPW; ++t)
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-      comb[(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * 17 + li] = (T)acc[t][r];
+        comb[(blk * Hy + (lt0 + t * lts) * 16 + Eng::acc_row(lk, r)) * ldc + w * 16 + li] = (T)acc[w][t][r];
   __syncthreads();
-  for (int e = threadIdx.x; e < Ay * 16; e += nthr) {
-    const int k = e >> 4, c = e & 15;
-    const T E = comb[k * 17 + c], O = comb[(Hy + k) * 17 + c];
+  for (int e = threadIdx.x; e < Ay * NC; e += nthr) {
+    const int k = e / NC, c = e % NC;
+    const T E = comb[k * ldc + c], O = comb[(Hy + k) * ldc + c];
     const int r2 = my - 1 - k;
     dst[(long long)k * Mx + c] = E + O;
     if (r2 != k) dst[(long long)r2 * Mx + c] = E - O;
@@ -797,14 +956,19 @@ inline int waves_for(int M) {
 }
 
 // ---- autotuned launch shapes ---------------------------------------------------------------
-// A launch shape is (waves per workgroup, deep prefetch ring).  Every shape runs the same
-// multiply-adds in the same order, so the choice changes the speed only, never the result.
-// Choices are measured per (kernel, engine, extent, slices) and kept for the process (and in
-// the file KKTDD_TUNE_CACHE names, one JSON object per line, when that is set).
+// A launch shape is (waves per workgroup, deep prefetch ring, blocks per workgroup: 16-row
+// blocks of the row kernel or 16-column blocks of the column kernel).  Every shape runs the
+// same multiply-adds in the same order, so the choice changes the speed only, never the
+// result.  Choices are measured per (kernel, engine, extent, slices) and kept for the process
+// (and in the file KKTDD_TUNE_CACHE names, one JSON object per line, when that is set).
 struct Shape {
   int nw;
   int deep;
+  int width;
 };
+
+// LDS one workgroup may take on gfx950.
+constexpr size_t kMaxLds = 160 * 1024;
 using TuneKey = std::array<int, 4>;   // kind (0 rows, 1 cols), engine, M, slices
 std::mutex g_tune_mu;
 std::map<TuneKey, Shape> g_tuned;
@@ -824,10 +988,10 @@ void tune_load_locked() {
   if (!f) return;
   char line[256];
   while (std::fgets(line, sizeof line, f)) {
-    int kind, eng, M, ns, nw, deep;
+    int kind, eng, M, ns, nw, deep, width;
     if (std::sscanf(line, "{\"kind\": %d, \"engine\": %d, \"M\": %d, \"slices\": %d, \"waves\": %d, "
-                    "\"deep\": %d", &kind, &eng, &M, &ns, &nw, &deep) == 6)
-      g_tuned[{kind, eng, M, ns}] = Shape{nw, deep};
+                    "\"deep\": %d, \"width\": %d", &kind, &eng, &M, &ns, &nw, &deep, &width) == 7)
+      g_tuned[{kind, eng, M, ns}] = Shape{nw, deep, width};
   }
   std::fclose(f);
 }
@@ -837,7 +1001,7 @@ Shape tuned_shape(int kind, int eng, int M, int nslices) {
   tune_load_locked();
   auto it = g_tuned.find({kind, eng, M, nslices});
   if (it != g_tuned.end()) return it->second;
-  return Shape{waves_for(M), 0};
+  return Shape{waves_for(M), 0, 1};
 }
 
 template <typename Eng> constexpr int engine_id();
@@ -876,76 +1040,127 @@ inline double folded_flops(int m) {
   return 2.0 * (A * A + B * B);
 }
 
-template <typename Eng, int TPW, int PD>
+template <typename Eng, int TPW, int PD, int RB>
 int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
-  const size_t lds = Eng::rows_lds_total(g.Mx);
-  if (int e = allow_lds(k_rows<Eng, TPW, PD>, lds)) return e;
+  const size_t lds = Eng::template rows_lds_total<RB>(g.Mx);
+  if (lds > kMaxLds) return set_error(KKTDD_EINVAL, "row-kernel shape needs more LDS than a CU has");
+  if (int e = allow_lds(k_rows<Eng, TPW, PD, RB>, lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
   RowArgs<typename Eng::data_t> la = a;
   la.nsl = slice_per_xcd(g, nslices, sizeof(typename Eng::data_t)) ? nslices : 0;
   // row blocks past the interior would only write padding rows, which nothing reads
-  hipLaunchKernelGGL((k_rows<Eng, TPW, PD>), sweep_grid((g.my + 15) / 16, nslices, la.nsl),
+  hipLaunchKernelGGL((k_rows<Eng, TPW, PD, RB>), sweep_grid((g.my + 16 * RB - 1) / (16 * RB), nslices, la.nsl),
                      dim3(64 * nw), lds, s, g, la);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, ngemm * nslices * (double)g.my * folded_flops(g.mx));
   return 0;
 }
 
-template <typename Eng, int TPW, int PD>
+template <typename Eng, int TPW, int PD, int CB>
 int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
-  const size_t lds = Eng::cols_lds_total(g.My);
-  if (int e = allow_lds(k_cols<Eng, TPW, PD>, lds)) return e;
+  const size_t lds = Eng::template cols_lds_total<CB>(g.My);
+  if (lds > kMaxLds || (g.Mx / 16) % CB != 0)
+    return set_error(KKTDD_EINVAL, "column-kernel shape does not fit the extent or the LDS");
+  if (int e = allow_lds(k_cols<Eng, TPW, PD, CB>, lds)) return e;
   prof_begin(kclass, s);
   ColArgs<typename Eng::data_t> la = a;
   la.nsl = slice_per_xcd(g, nslices, sizeof(typename Eng::data_t)) ? nslices : 0;
-  hipLaunchKernelGGL((k_cols<Eng, TPW, PD>), sweep_grid(g.Mx / 16, nslices, la.nsl), dim3(64 * nw),
+  hipLaunchKernelGGL((k_cols<Eng, TPW, PD, CB>), sweep_grid(g.Mx / (16 * CB), nslices, la.nsl), dim3(64 * nw),
                      lds, s, g, la);
   KKT_HIP(hipGetLastError());
   prof_end(kclass, s, 0.0, (1 + a.two) * nslices * (double)g.mx * folded_flops(g.my));
   return 0;
 }
 
-// (tiles per wave, deep ring) -> instantiation; deep rings exist for up to four tiles.
-#define KKT_TPW_DISPATCH(FN, TPWV, DEEP, ...)                                            \
+// Whether a workgroup of `width` blocks fits the LDS (and, for the column kernel, the tile
+// count of the x extent).
+template <typename Eng>
+bool width_fits(int kind, const Geom& g, int width) {
+  size_t lds = 0;
+  switch (width) {
+    case 1: lds = kind == 0 ? Eng::template rows_lds_total<1>(g.Mx) : Eng::template cols_lds_total<1>(g.My); break;
+    case 2: lds = kind == 0 ? Eng::template rows_lds_total<2>(g.Mx) : Eng::template cols_lds_total<2>(g.My); break;
+    case 4: lds = kind == 0 ? Eng::template rows_lds_total<4>(g.Mx) : Eng::template cols_lds_total<4>(g.My); break;
+    default: return false;
+  }
+  return lds <= kMaxLds && (kind == 0 || (g.Mx / 16) % width == 0);
+}
+
+// (tiles per wave, deep ring, blocks per workgroup) -> instantiation; deep rings exist for up
+// to four tiles and one block, several blocks for up to four tiles and the default ring.
+#define KKT_W_DISPATCH(FN, TPWV, W, ...)                                                 \
+  switch (W) {                                                                           \
+    case 2: return FN<Eng, TPWV, kPDDefault, 2>(__VA_ARGS__);                            \
+    case 4: return FN<Eng, TPWV, kPDDefault, 4>(__VA_ARGS__);                            \
+    default: return set_error(KKTDD_EINVAL, "unsupported blocks per workgroup");         \
+  }
+#define KKT_TPW_DISPATCH(FN, TPWV, DEEP, W, ...)                                         \
+  if ((W) != 1) {                                                                        \
+    if (DEEP) return set_error(KKTDD_EINVAL, "deep rings take one block per workgroup"); \
+    switch (TPWV) {                                                                      \
+      case 1: KKT_W_DISPATCH(FN, 1, W, __VA_ARGS__)                                      \
+      case 2: KKT_W_DISPATCH(FN, 2, W, __VA_ARGS__)                                      \
+      case 3: KKT_W_DISPATCH(FN, 3, W, __VA_ARGS__)                                      \
+      case 4: KKT_W_DISPATCH(FN, 4, W, __VA_ARGS__)                                      \
+      default: return set_error(KKTDD_EINVAL, "several blocks need <= 4 tiles per wave"); \
+    }                                                                                    \
+  }                                                                                      \
   switch (TPWV) {                                                                        \
-    case 1: return (DEEP) ? FN<Eng, 1, deep_prefetch<1>()>(__VA_ARGS__)                  \
-                          : FN<Eng, 1, kPDDefault>(__VA_ARGS__);                         \
-    case 2: return (DEEP) ? FN<Eng, 2, deep_prefetch<2>()>(__VA_ARGS__)                  \
-                          : FN<Eng, 2, kPDDefault>(__VA_ARGS__);                         \
-    case 3: return (DEEP) ? FN<Eng, 3, deep_prefetch<3>()>(__VA_ARGS__)                  \
-                          : FN<Eng, 3, kPDDefault>(__VA_ARGS__);                         \
-    case 4: return (DEEP) ? FN<Eng, 4, deep_prefetch<4>()>(__VA_ARGS__)                  \
-                          : FN<Eng, 4, kPDDefault>(__VA_ARGS__);                         \
-    case 5: return FN<Eng, 5, kPDDefault>(__VA_ARGS__);                                  \
-    case 6: return FN<Eng, 6, kPDDefault>(__VA_ARGS__);                                  \
-    case 7: return FN<Eng, 7, kPDDefault>(__VA_ARGS__);                                  \
-    case 8: return FN<Eng, 8, kPDDefault>(__VA_ARGS__);                                  \
+    case 1: return (DEEP) ? FN<Eng, 1, deep_prefetch<1>(), 1>(__VA_ARGS__)               \
+                          : FN<Eng, 1, kPDDefault, 1>(__VA_ARGS__);                      \
+    case 2: return (DEEP) ? FN<Eng, 2, deep_prefetch<2>(), 1>(__VA_ARGS__)               \
+                          : FN<Eng, 2, kPDDefault, 1>(__VA_ARGS__);                      \
+    case 3: return (DEEP) ? FN<Eng, 3, deep_prefetch<3>(), 1>(__VA_ARGS__)               \
+                          : FN<Eng, 3, kPDDefault, 1>(__VA_ARGS__);                      \
+    case 4: return (DEEP) ? FN<Eng, 4, deep_prefetch<4>(), 1>(__VA_ARGS__)               \
+                          : FN<Eng, 4, kPDDefault, 1>(__VA_ARGS__);                      \
+    case 5: return FN<Eng, 5, kPDDefault, 1>(__VA_ARGS__);                               \
+    case 6: return FN<Eng, 6, kPDDefault, 1>(__VA_ARGS__);                               \
+    case 7: return FN<Eng, 7, kPDDefault, 1>(__VA_ARGS__);                               \
+    case 8: return FN<Eng, 8, kPDDefault, 1>(__VA_ARGS__);                               \
     default: return set_error(KKTDD_EINVAL, "unsupported tile count");                   \
   }
 
 template <typename Eng>
 int rows_shape(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, Shape sh,
                int kclass, hipStream_t s) {
-  KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / sh.nw, sh.deep, g, a, nslices, sh.nw, kclass, s)
+  KKT_TPW_DISPATCH(rows_t, g.Mx / 16 / sh.nw, sh.deep, sh.width, g, a, nslices, sh.nw, kclass, s)
 }
 
 template <typename Eng>
 int cols_shape(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, Shape sh,
                int kclass, hipStream_t s) {
-  KKT_TPW_DISPATCH(cols_t, g.My / 16 / sh.nw, sh.deep, g, a, nslices, sh.nw, kclass, s)
+  KKT_TPW_DISPATCH(cols_t, g.My / 16 / sh.nw, sh.deep, sh.width, g, a, nslices, sh.nw, kclass, s)
+}
+
+// A shape kept for another extent's geometry may not fit this one (same padded extent,
+// other tile counts along the other axis): fall back to one block per workgroup.
+template <typename Eng>
+Shape fitted(int kind, const Geom& g, Shape sh) {
+  if (sh.width != 1 && !width_fits<Eng>(kind, g, sh.width)) sh.width = 1;
+  return sh;
 }
 
 template <typename Eng>
 int rows(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
-  return rows_shape<Eng>(g, a, nslices, tuned_shape(0, engine_id<Eng>(), g.Mx, nslices), kclass, s);
+  return rows_shape<Eng>(g, a, nslices, fitted<Eng>(0, g, tuned_shape(0, engine_id<Eng>(), g.Mx, nslices)),
+                         kclass, s);
 }
 
 template <typename Eng>
 int cols(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int kclass, hipStream_t s) {
-  return cols_shape<Eng>(g, a, nslices, tuned_shape(1, engine_id<Eng>(), g.My, nslices), kclass, s);
+  return cols_shape<Eng>(g, a, nslices, fitted<Eng>(1, g, tuned_shape(1, engine_id<Eng>(), g.My, nslices)),
+                         kclass, s);
+}
+
+// r' in the engine's sweep precision: float64 for the float64 engine, float32 otherwise.
+template <typename T>
+void set_rin(RowArgs<T>& r, const void* rprime) {
+  if constexpr (sizeof(T) == 8) r.rin = static_cast<const double*>(rprime);
+  else r.rin32 = static_cast<const float*>(rprime);
 }
 
 template <typename T>
@@ -984,7 +1199,7 @@ int spatial_solve_t(const Geom& g, const void* Sx, const void* Sy, const void* i
 // subdomain runs the same L steps.
 template <typename Eng>
 int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
-             const double* rprime, const double* c0, double* zw, void* Tb, void* Ub, void* Yb,
+             const void* rprime, const double* c0, double* zw, void* Tb, void* Ub, void* Yb,
              hipStream_t s) {
   using T = typename Eng::data_t;
   const long long MM = g.padded();
@@ -1006,7 +1221,7 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
     }
     r.b_mode = B_RPRIME_PLUS_Y;
     r.b_step = j;
-    r.rin = rprime;
+    set_rin<T>(r, rprime);
     r.g2_out = Tbuf;
     r.g2_stride = MM;
     if (int e = rows<Eng>(g, r, nd, KKTDD_K_SWEEP_ROWS, s)) return e;
@@ -1054,12 +1269,14 @@ int sweeps_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam,
 
 template <typename Eng>
 int dst_forward_t(const Geom& g, const void* Sx, const void* Sy, const double* in,
-                  const double* dscale, void* tmp, void* out, int nslices, hipStream_t s) {
+                  const double* dscale, void* tmp, void* out, int nslices, hipStream_t s,
+                  const float* in32) {
   using T = typename Eng::data_t;
   const long long MM = g.padded();
   RowArgs<T> r = row_args<T>(Sx);
   r.b_mode = B_INPUT;
   r.rin = in;
+  r.rin32 = in32;
   r.in_scale = dscale;
   r.g2_out = static_cast<T*>(tmp);
   r.g2_stride = MM;
@@ -1091,7 +1308,7 @@ int dst_inverse_t(const Geom& g, const void* Sx, const void* Sy, const void* in,
 // slices (both products of each kernel, on the handle's work buffers) and keep the fastest.
 template <typename Eng>
 int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam, void* bufA,
-               void* bufB, int nslices, hipStream_t s) {
+               void* bufB, int nslices, const void* rprime, void* ybuf, hipStream_t s) {
   using T = typename Eng::data_t;
   const long long MM = g.padded();
   RowArgs<T> r = row_args<T>(Sx);
@@ -1100,6 +1317,14 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
   r.b_mode = B_H_Y;
   r.g2_out = static_cast<T*>(bufB);
   r.g2_stride = MM;
+  if (rprime && ybuf) {
+    // the per-step sweeps: time the forward-sweep row launch, which also reads r' and stores y
+    r.b_mode = B_RPRIME_PLUS_Y;
+    r.b_step = g.delta;
+    set_rin<T>(r, rprime);
+    r.ystore = static_cast<T*>(ybuf);
+    r.ystore_stride = (long long)g.L * MM;
+  }
   ColArgs<T> c{Sy, static_cast<const T*>(bufA), MM, static_cast<const T*>(invlam), 1, 1,
                static_cast<T*>(bufB), MM};
   hipEvent_t e0, e1;
@@ -1123,12 +1348,16 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     int nc = 0;
     // (the deep rings are not candidates: with the folded products' half-length k-loops they
     // measured slower than the default ring at every extent; tune_set can still select them)
-    cand[nc++] = Shape{waves_for(M), 0};
-    for (int nw : {2, 4, 8, t}) {
-      if (nw < 2 || nw > 8 || (nw & 1) || t % nw != 0 || t / nw > 8) continue;
-      bool seen = false;
-      for (int i = 0; i < nc; ++i) seen = seen || cand[i].nw == nw;
-      if (!seen && nc < 32) cand[nc++] = Shape{nw, 0};
+    cand[nc++] = Shape{waves_for(M), 0, 1};
+    for (int width : {1, 2, 4}) {
+      if (!width_fits<Eng>(kind, g, width)) continue;
+      for (int nw : {waves_for(M), 2, 4, 8, t}) {
+        if (nw < 2 || nw > 8 || (nw & 1) || t % nw != 0 || t / nw > 8) continue;
+        if (width > 1 && t / nw > 4) continue;
+        bool seen = false;
+        for (int i = 0; i < nc; ++i) seen = seen || (cand[i].nw == nw && cand[i].width == width);
+        if (!seen && nc < 32) cand[nc++] = Shape{nw, 0, width};
+      }
     }
     // rounds of 4 launches per candidate, candidates interleaved; a candidate's time is its
     // fastest round.  The default shape is kept unless another is at least 5% faster.
@@ -1157,6 +1386,10 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
         best_round[ci] = std::min(best_round[ci], 1e3f * ms / 4.f);
       }
     }
+    if (const char* v = std::getenv("KKTDD_TUNE_LOG"); v && std::atoi(v) != 0)
+      for (int ci = 0; ci < nc; ++ci)
+        std::fprintf(stderr, "kktdd tune: kind %d engine %d M %d slices %d waves %d width %d: %.2f us\n", kind,
+                     engine_id<Eng>(), M, nslices, cand[ci].nw, cand[ci].width, best_round[ci]);
     Shape best = cand[0];
     float best_us = best_round[0];
     for (int ci = 1; ci < nc; ++ci)
@@ -1170,8 +1403,8 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     if (const char* path = tune_path()) {
       if (FILE* f = std::fopen(path, "a")) {
         std::fprintf(f, "{\"kind\": %d, \"engine\": %d, \"M\": %d, \"slices\": %d, \"waves\": %d, "
-                        "\"deep\": %d, \"us\": %.2f}\n", kind, engine_id<Eng>(), M, nslices, best.nw,
-                     best.deep, best_us);
+                        "\"deep\": %d, \"width\": %d, \"us\": %.2f}\n", kind, engine_id<Eng>(), M, nslices,
+                     best.nw, best.deep, best.width, best_us);
         std::fclose(f);
       }
     }
@@ -1195,8 +1428,10 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
 
 int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const double* in, const double* dscale, void* tmp, void* out, int nslices,
-                       hipStream_t s) {
-  KKT_ENGINE_DISPATCH(precision, dst_forward_t, g, Sx, Sy, in, dscale, tmp, out, nslices, s)
+                       hipStream_t s, const float* in32) {
+  if (in32 && (precision == KKTDD_FP64 || dscale))
+    return set_error(KKTDD_EINVAL, "float32 transform input needs a reduced-precision engine and no scale");
+  KKT_ENGINE_DISPATCH(precision, dst_forward_t, g, Sx, Sy, in, dscale, tmp, out, nslices, s, in32)
 }
 
 int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
@@ -1213,7 +1448,7 @@ int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const voi
 }
 
 int launch_sweeps(const Geom& g, int precision, const void* Sx, const void* Sy,
-                  const void* invlam, const double* rprime, const double* c0, double* zw,
+                  const void* invlam, const void* rprime, const double* c0, double* zw,
                   void* Tbuf, void* Ubuf, void* Ybuf, hipStream_t s) {
   KKT_ENGINE_DISPATCH(precision, sweeps_t, g, Sx, Sy, invlam, rprime, c0, zw, Tbuf, Ubuf, Ybuf, s)
 }
@@ -1249,31 +1484,34 @@ int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const 
 
 namespace kktdd {
 
-int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep) {
+int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep, int width) {
   const int t = extent / 16;
   if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 32 ||
       extent % 32 != 0 || nslices < 1 || waves < 2 || waves > 8 || (waves & 1) || t % waves != 0 ||
-      t / waves > 8 || deep < 0 || deep > 1)
+      t / waves > 8 || deep < 0 || deep > 1 || (width != 1 && width != 2 && width != 4) ||
+      (width > 1 && (deep || t / waves > 4)))
     return set_error(KKTDD_EINVAL, "invalid launch shape");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
-  g_tuned[{kind, precision, extent, nslices}] = Shape{waves, deep};
+  g_tuned[{kind, precision, extent, nslices}] = Shape{waves, deep, width};
   return 0;
 }
 
-int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep) {
-  if (!waves || !deep || extent < 32 || extent % 32 != 0)
+int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep, int* width) {
+  if (!waves || !deep || !width || extent < 32 || extent % 32 != 0)
     return set_error(KKTDD_EINVAL, "invalid launch-shape query");
   const Shape sh = tuned_shape(kind, precision, extent, nslices);
   *waves = sh.nw;
   *deep = sh.deep;
+  *width = sh.width;
   return 0;
 }
 
 int launch_autotune(const Geom& g, int precision, const void* Sx, const void* Sy,
-                    const void* invlam, void* bufA, void* bufB, int nslices, hipStream_t s) {
+                    const void* invlam, void* bufA, void* bufB, int nslices, const void* rprime,
+                    void* ybuf, hipStream_t s) {
   if (nslices <= 0) return 0;
-  KKT_ENGINE_DISPATCH(precision, autotune_t, g, Sx, Sy, invlam, bufA, bufB, nslices, s)
+  KKT_ENGINE_DISPATCH(precision, autotune_t, g, Sx, Sy, invlam, bufA, bufB, nslices, rprime, ybuf, s)
 }
 
 }  // namespace kktdd

@@ -107,10 +107,11 @@ int launch_apply_D(const Geom& g, const double* in, double* out, int nslices, do
 int launch_spatial_solve(const Geom& g, int precision, const void* Sx, const void* Sy,
                          const void* invlam, const double* b, double* x, int nslices,
                          void* work1, void* work2, hipStream_t s);
-// Fine-level RASQ sweeps of Eq. (13) for every subdomain: reads r' (nt slices, float64),
-// writes z_w (nt slices) = c + x at owned nodes, c from the coarse slots c0 (nullptr: 0).
+// Fine-level RASQ sweeps of Eq. (13) for every subdomain: reads r' (nt slices, float64 for
+// the float64 engine, else float32), writes z_w (nt slices) = c + x at owned nodes, c from the
+// coarse slots c0 (nullptr: 0).
 int launch_sweeps(const Geom& g, int precision, const void* Sx, const void* Sy,
-                  const void* invlam, const double* rprime, const double* c0, double* zw,
+                  const void* invlam, const void* rprime, const double* c0, double* zw,
                   void* Tbuf, void* Ubuf, void* Ybuf, hipStream_t s);
 // Coarse sine transforms (float64): forward r0 (nc unpadded slices) -> rhat (padded), and
 // inverse chat (padded) -> c0 (unpadded, with the 4/(nx ny) normalisation).
@@ -121,24 +122,28 @@ int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const 
 
 // Batched 2-D sine transforms of nslices slices in the handle's precision (folded products;
 // padded mode space in the order of mode_pos):
-//   forward  out = S_y (scale*in) S_x   (in: unpadded float64 slices; out, tmp: padded)
+//   forward  out = S_y (scale*in) S_x   (in: unpadded float64 slices, or in32: float32 ones
+//            for the reduced-precision engines; out, tmp: padded)
 //   inverse  out = norm * S_y in S_x    (in, tmp: padded; out: unpadded float64 slices),
 //            plus the coarse part Z c0 when c0 != nullptr (the slices are time-nodes 1..nt)
 int launch_dst_forward(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const double* in, const double* dscale, void* tmp, void* out, int nslices,
-                       hipStream_t s);
+                       hipStream_t s, const float* in32 = nullptr);
 int launch_dst_inverse(const Geom& g, int precision, const void* Sx, const void* Sy,
                        const void* in, void* tmp, double* out, int nslices, double norm,
                        const double* c0, hipStream_t s);
 
 // ---- modal.hip: transform-hoisted Schur block (sine-mode space) --------------------------
 // Autotuner: measure the launch shapes of the row and column kernels for this extent and
-// slice count on two work buffers (each nslices padded slices) and keep the fastest.
+// slice count on two work buffers (each nslices padded slices) and keep the fastest.  With
+// r' (nt slices in the sweep precision, zeroed) and the forward-sweep store, the row launches are timed as
+// forward-sweep steps (reading r', storing y); else as plain chained products.
 int launch_autotune(const Geom& g, int precision, const void* Sx, const void* Sy,
-                    const void* invlam, void* bufA, void* bufB, int nslices, hipStream_t s);
+                    const void* invlam, void* bufA, void* bufB, int nslices, const void* rprime,
+                    void* ybuf, hipStream_t s);
 
-int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep);
-int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep);
+int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep, int width);
+int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep, int* width);
 
 int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
                           hipStream_t s);
@@ -159,9 +164,11 @@ int launch_coarse_factor(const Geom& g, const double* G2, const double* G0, cons
                          hipStream_t s);
 int launch_coarse_solve(const Geom& g, const double* fac, double* xhat, hipStream_t s);
 // r' = scale*r_w - S_hat c with c prolonged from c0; c0/Dc0/DDc0 may be nullptr (no coarse).
+// Computed in float64 and stored as float32 (f32 != 0: the reduced-precision sweeps, which
+// round it to float32 when they read it) or float64.
 int launch_residual_prime(const Geom& g, const double* rw, const double* dscale,
                           const double* c0, const double* Dc0, const double* DDc0,
-                          double* rprime, hipStream_t s);
+                          void* rprime, int f32, hipStream_t s);
 
 // ---- krylov.hip: Arnoldi and vector kernels ------------------------------------------------
 // Per-block partial sums of the raw products <V_i, w> for i < nv and, if want_norm, <w, w>
@@ -239,7 +246,7 @@ struct kktdd_handle {
   double *lamx = nullptr, *lamy = nullptr;     // dt*nu*lambda (unpadded)
   // per-step sweeps
   void *Tbuf = nullptr, *Ubuf = nullptr, *Ybuf = nullptr;
-  double* rprime = nullptr;
+  void* rprime = nullptr;                      // r', P elements of the sweep precision
   // modal (transform-hoisted) sweeps
   void *Rhat = nullptr, *Mtmp = nullptr;
   double* Ysc = nullptr;

@@ -49,22 +49,38 @@ k_kkt_apply(Geom g, const double* __restrict__ xu, const double* __restrict__ xz
   }
   const double cx = g.cx, cy = g.cy, h = g.h, oh = g.omega * g.h, dt = g.dt;
   const long long nxy = g.nxy;
+  // Operands of one time-node.  Those of node n+1 are requested before node n is computed,
+  // so every thread keeps two nodes' loads in flight.
+  struct Node {
+    double u, uE, uW, uN, uS, wE, wW, wN, wS, z, w_next;
+  };
+  auto load = [&](int n, Node& v) {
+    const long long b = n * nxy + pt;
+    v.u = xu[b];
+    v.uE = hasE ? xu[b + 1] : 0.0;
+    v.uW = hasW ? xu[b - 1] : 0.0;
+    v.uN = hasN ? xu[b + g.mx] : 0.0;
+    v.uS = hasS ? xu[b - g.mx] : 0.0;
+    v.wE = hasE ? xw[b + 1] : 0.0;
+    v.wW = hasW ? xw[b - 1] : 0.0;
+    v.wN = hasN ? xw[b + g.mx] : 0.0;
+    v.wS = hasS ? xw[b - g.mx] : 0.0;
+    v.z = xz[b];
+    v.w_next = n + 1 < g.nt ? xw[b + nxy] : 0.0;
+  };
   double u_prev = n0 > 0 ? xu[(n0 - 1) * nxy + pt] : 0.0;
   double w_c = xw[n0 * nxy + pt];
+  Node cur, nxt;
+  load(n0, cur);
   for (int n = n0; n < n1; ++n) {
+    if (n + 1 < n1) load(n + 1, nxt);
     const long long b = n * nxy + pt;
-    const double u_c = xu[b];
-    const double uE = hasE ? xu[b + 1] : 0.0, uW = hasW ? xu[b - 1] : 0.0;
-    const double uN = hasN ? xu[b + g.mx] : 0.0, uS = hasS ? xu[b - g.mx] : 0.0;
-    const double wE = hasE ? xw[b + 1] : 0.0, wW = hasW ? xw[b - 1] : 0.0;
-    const double wN = hasN ? xw[b + g.mx] : 0.0, wS = hasS ? xw[b - g.mx] : 0.0;
-    const double w_next = n + 1 < g.nt ? xw[b + nxy] : 0.0;
-    const double z_c = xz[b];
-    const double Bu = u_c + cx * (2.0 * u_c - uE - uW) + cy * (2.0 * u_c - uN - uS);
-    const double Bw = w_c + cx * (2.0 * w_c - wE - wW) + cy * (2.0 * w_c - wN - wS);
-    double ru = h * su * u_c + sw * (Bw - w_next);
-    double rz = oh * sz * z_c - dt * sw * w_c;
-    double rw = su * (Bu - u_prev) - dt * sz * z_c;
+    const double u_c = cur.u;
+    const double Bu = u_c + cx * (2.0 * u_c - cur.uE - cur.uW) + cy * (2.0 * u_c - cur.uN - cur.uS);
+    const double Bw = w_c + cx * (2.0 * w_c - cur.wE - cur.wW) + cy * (2.0 * w_c - cur.wN - cur.wS);
+    double ru = h * su * u_c + sw * (Bw - cur.w_next);
+    double rz = oh * sz * cur.z - dt * sw * w_c;
+    double rw = su * (Bu - u_prev) - dt * sz * cur.z;
     if (f) {
       ru = f[b] - ru;
       rz = f[g.P + b] - rz;
@@ -74,7 +90,8 @@ k_kkt_apply(Geom g, const double* __restrict__ xu, const double* __restrict__ xz
     yz[b] = rz;
     yw[b] = rw;
     u_prev = u_c;
-    w_c = w_next;
+    w_c = cur.w_next;
+    cur = nxt;
   }
 }
 

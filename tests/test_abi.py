@@ -138,18 +138,24 @@ def test_variant_memory_plan():
 
 def test_launch_shape_table(lib):
     from paper_2305_04421_amd import _lib
-    w, d = ctypes.c_int32(), ctypes.c_int32()
-    # no entry: the default shape (8 waves for 32 tiles, shallow ring)
-    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d)) == 0
-    assert (w.value, d.value) == (8, 0)
-    assert lib.kkt_tune_set(1, _lib.FP32, 512, 7, 4, 1) == 0
-    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d)) == 0
-    assert (w.value, d.value) == (4, 1)
+    w, d, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    # no entry: the default shape (8 waves for 32 tiles, shallow ring, one block)
+    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d), ctypes.byref(b)) == 0
+    assert (w.value, d.value, b.value) == (8, 0, 1)
+    assert lib.kkt_tune_set(1, _lib.FP32, 512, 7, 4, 1, 1) == 0
+    assert lib.kkt_tune_get(1, _lib.FP32, 512, 7, ctypes.byref(w), ctypes.byref(d), ctypes.byref(b)) == 0
+    assert (w.value, d.value, b.value) == (4, 1, 1)
+    assert lib.kkt_tune_set(0, _lib.BF16X3, 512, 7, 8, 0, 4) == 0
+    assert lib.kkt_tune_get(0, _lib.BF16X3, 512, 7, ctypes.byref(w), ctypes.byref(d), ctypes.byref(b)) == 0
+    assert (w.value, d.value, b.value) == (8, 0, 4)
     # wave counts must be even (each wave stays inside one half of the folded transform),
-    # extents multiples of 32, at most 8 tiles per wave
-    for bad in [(2, 0, 128, 4, 8, 0), (0, 9, 128, 4, 8, 0), (0, 0, 100, 4, 4, 0), (0, 0, 128, 4, 3, 0),
-                (0, 0, 128, 4, 1, 0), (0, 0, 16, 4, 2, 0), (0, 0, 512, 4, 2, 0), (0, 0, 128, 0, 8, 0),
-                (0, 0, 128, 4, 8, 2)]:
+    # extents multiples of 32, at most 8 tiles per wave; widths 1, 2 or 4, and a width above 1
+    # takes the shallow ring and at most 4 tiles per wave
+    for bad in [(2, 0, 128, 4, 8, 0, 1), (0, 9, 128, 4, 8, 0, 1), (0, 0, 100, 4, 4, 0, 1),
+                (0, 0, 128, 4, 3, 0, 1), (0, 0, 128, 4, 1, 0, 1), (0, 0, 16, 4, 2, 0, 1),
+                (0, 0, 512, 4, 2, 0, 1), (0, 0, 128, 0, 8, 0, 1), (0, 0, 128, 4, 8, 2, 1),
+                (0, 0, 128, 4, 8, 0, 3), (0, 0, 128, 4, 8, 1, 2), (0, 0, 512, 4, 4, 0, 2),
+                (0, 0, 128, 4, 8, 0, 0)]:
         assert lib.kkt_tune_set(*bad) == _lib.EINVAL, bad
 
 

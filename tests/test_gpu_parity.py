@@ -119,35 +119,71 @@ def test_precond_degenerate_one_level(sweep):
     assert relerr_blocks(z, pc.apply_Pinv(p, r)) <= 1e-12
 
 
-@pytest.mark.parametrize("precision,sweep", [("fp64", "step"), ("fp32", "step"), ("bf16x3", "step"),
-                                             ("fp64", "modal")])
-def test_launch_shapes_give_identical_results(precision, sweep):
-    """Every launch shape of the transform kernels (waves per workgroup, prefetch depth)
-    performs the same operations in the same order: the preconditioner is bitwise equal."""
+# (waves, deep ring, blocks per workgroup) of the row kernel and of the column kernel
+SHAPE_PAIRS = [((8, 0, 1), (4, 1, 1)), ((8, 1, 1), (2, 0, 1)), ((4, 1, 1), (2, 1, 1)), ((2, 0, 1), (4, 0, 1)),
+               ((4, 0, 1), (2, 1, 1)), ((8, 0, 2), (4, 0, 2)), ((4, 0, 4), (2, 0, 4)), ((2, 0, 2), (4, 0, 4)),
+               ((8, 0, 4), (2, 0, 2))]
+
+
+def _shape_sweep(lib, prec, extents, ns, run, pairs):
+    """run() under every (rows, cols) launch shape of `pairs`; restores the table after."""
     import ctypes
+    saved = []
+    for kind, M in ((0, extents[0]), (1, extents[1])):
+        w, d, b = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        assert lib.kkt_tune_get(kind, prec, M, ns, ctypes.byref(w), ctypes.byref(d), ctypes.byref(b)) == 0
+        saved.append((kind, M, w.value, d.value, b.value))
+    out = []
+    try:
+        for rows_shape, cols_shape in pairs:
+            assert lib.kkt_tune_set(0, prec, extents[0], ns, *rows_shape) == 0
+            assert lib.kkt_tune_set(1, prec, extents[1], ns, *cols_shape) == 0
+            out.append(((rows_shape, cols_shape), run()))
+    finally:
+        for kind, M, w, d, b in saved:
+            lib.kkt_tune_set(kind, prec, M, ns, w, d, b)
+    return out
+
+
+@pytest.mark.parametrize("precision,sweep", [(p, "step") for p in ("fp64", "fp32", "bf16x6", "bf16x3", "bf16")] +
+                                            [("fp64", "modal"), ("fp32", "modal")])
+@pytest.mark.parametrize("name", ["full_tiles_overlap_k", "ragged_tiles"])
+def test_launch_shapes_give_identical_results(name, precision, sweep):
+    """Every launch shape of the transform kernels (waves per workgroup, prefetch depth, 16-row
+    or 16-column blocks per workgroup) performs the same operations in the same order: the
+    preconditioner is bitwise equal.  ragged_tiles has fewer row blocks than some widths."""
     from paper_2305_04421_amd import _lib
     lib = _lib.load()
-    params = CASES["full_tiles_overlap_k"]    # padded extents 128 (x) and 64 (y), 4 subdomains
+    params = CASES[name]    # padded extents 128 x 64 (4 subdomains), 64 x 32 (3 subdomains)
     p = Problem(**params).validate()
     r = dev(wl.random_field((3,) + p.field_shape, 21))
     prec = _lib.PRECISIONS[precision]
+    extents = (128, 64) if name == "full_tiles_overlap_k" else (64, 32)
+    pairs = SHAPE_PAIRS if name == "full_tiles_overlap_k" else [
+        ((4, 0, 1), (2, 0, 1)), ((4, 0, 2), (2, 0, 2)), ((4, 0, 4), (2, 0, 4)), ((2, 0, 4), (2, 0, 1))]
     with solver(params, precision, sweep=sweep) as S:
         ns = p.nt if sweep == "modal" else p.n_sub
-        saved = []
-        for kind, M in ((0, 128), (1, 64)):
-            w, d = ctypes.c_int32(), ctypes.c_int32()
-            assert lib.kkt_tune_get(kind, prec, M, ns, ctypes.byref(w), ctypes.byref(d)) == 0
-            saved.append((kind, M, w.value, d.value))
         ref = S.precond(r).clone()
-        try:
-            for rows_shape, cols_shape in [((8, 0), (4, 1)), ((8, 1), (2, 0)), ((4, 1), (2, 1)),
-                                           ((2, 0), (4, 0)), ((4, 0), (2, 1))]:
-                assert lib.kkt_tune_set(0, prec, 128, ns, *rows_shape) == 0
-                assert lib.kkt_tune_set(1, prec, 64, ns, *cols_shape) == 0
-                assert torch.equal(S.precond(r), ref), (rows_shape, cols_shape)
-        finally:
-            for kind, M, w, d in saved:
-                lib.kkt_tune_set(kind, prec, M, ns, w, d)
+        for shapes, z in _shape_sweep(lib, prec, extents, ns, lambda: S.precond(r).clone(), pairs):
+            assert torch.equal(z, ref), shapes
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6", "bf16x3", "bf16"])
+def test_block_widths_give_identical_results_at_the_largest_extents(precision):
+    """The spatial solve at padded extents 384 x 512 (three and four tiles per wave, every
+    grid512 sweep launch) under each workgroup width: bitwise equal to one block per group."""
+    from paper_2305_04421_amd import _lib
+    lib = _lib.load()
+    params = wl.problem(nx=385, ny=512, nt=4, Lx=1.0, Ly=1.7, nu=0.05, omega=1e-3, n_sub=1, overlap=0, coarse=0)
+    p = Problem(**params).validate()
+    b = dev(wl.random_field((3,) + p.slice_shape, 108))
+    prec = _lib.PRECISIONS[precision]
+    pairs = [((8, 0, 1), (8, 0, 1)), ((8, 0, 2), (8, 0, 2)), ((8, 0, 4), (8, 0, 4)), ((8, 0, 2), (8, 0, 1))]
+    with solver(params, precision) as S:
+        out = _shape_sweep(lib, prec, (384, 512), 3, lambda: S.spatial_solve(b, 1.3).clone(), pairs)
+    ref = out[0][1]
+    for shapes, x in out[1:]:
+        assert torch.equal(x, ref), shapes
 
 
 PLACEMENT_CASES = dict(CASES, eleven_subdomains=wl.problem(nx=40, ny=33, nt=22, Lx=1.0, Ly=0.8, nu=0.4,
