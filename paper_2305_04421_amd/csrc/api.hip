@@ -57,6 +57,13 @@ bool poison_enabled() {
   return e && std::atoi(e) != 0;
 }
 
+// KKTDD_GRAPH=0 runs every Arnoldi step's launches from the stream instead of replaying them
+// as a HIP graph (default 1).  Read at every solve.
+bool graphs_enabled() {
+  const char* e = std::getenv("KKTDD_GRAPH");
+  return !(e && std::atoi(e) == 0);
+}
+
 // KKTDD_LOG=1: every fgmres_solve prints its residual-estimate history to stderr when it ends.
 bool log_enabled() {
   const char* e = std::getenv("KKTDD_LOG");
@@ -669,8 +676,62 @@ int autotune(kktdd_handle* H) {
   return 0;
 }
 
+// Drop the recorded Arnoldi steps (their kernel arguments point into the Krylov storage).
+void release_graphs(kktdd_handle* H) {
+  for (hipGraphExec_t& e : H->graph_exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  H->graph_exec.clear();
+  H->graph_ran.clear();
+}
+
+// One Arnoldi step's launches (the Schur-block application, the matvec and the DCGS2 passes
+// of basis slot j; no host synchronisation inside).  Its first run in a handle is eager; the
+// next one is recorded as a HIP graph by stream capture and launched; later runs replay the
+// graph.  The launches of slot j always take the same arguments (pointers into the handle's
+// fixed storage, the slot index), so a replay performs exactly the work the stream would.
+// Not used while the per-launch timer is on, with KKTDD_GRAPH=0, or on the NULL stream (which
+// cannot be captured; kkt_solve_batched always runs on private streams).
+template <typename F>
+int run_step(kktdd_handle* H, int j, F&& work) {
+  if (!graphs_enabled() || (t_prof && t_prof->on) || H->stream == nullptr) return work();
+  if (H->graph_gen != tune_generation()) {
+    release_graphs(H);   // launch shapes changed since the graphs were recorded
+    H->graph_gen = tune_generation();
+  }
+  if ((int)H->graph_exec.size() <= j) {
+    H->graph_exec.resize((size_t)j + 1, nullptr);
+    H->graph_ran.resize((size_t)j + 1, 0);
+  }
+  hipStream_t s = H->stream;
+  if (H->graph_exec[j]) {
+    KKT_HIP(hipGraphLaunch(H->graph_exec[j], s));
+    return 0;
+  }
+  if (!H->graph_ran[j]) {
+    H->graph_ran[j] = 1;
+    return work();
+  }
+  KKT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  const int e = work();
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(s, &graph);
+  if (e || ce != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return e ? e : hip_fail(ce, "hipStreamEndCapture", __FILE__, __LINE__);
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return hip_fail(ie, "hipGraphInstantiate", __FILE__, __LINE__);
+  H->graph_exec[j] = exec;
+  KKT_HIP(hipGraphLaunch(exec, s));
+  return 0;
+}
+
 int ensure_krylov(kktdd_handle* H, int R) {
   if (H->R >= R) return 0;
+  release_graphs(H);
   const Geom& g = H->g;
   // free the previous basis
   auto release = [&](void* p) {
@@ -837,6 +898,7 @@ int kkt_create(const kktdd_problem* prob_in, void* hip_stream, kktdd_handle** ou
 void kkt_destroy(kktdd_handle* H) {
   if (!H) return;
   (void)hipStreamSynchronize(H->stream);
+  release_graphs(H);
   for (void* p : H->allocations) (void)hipFree(p);
   if (H->host_sums) (void)hipHostFree(H->host_sums);
   if (H->host_hcol) (void)hipHostFree(H->host_hcol);
@@ -1076,12 +1138,15 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       double* vj = V + (long long)j * ldv;
       double* w = V + (long long)(j + 1) * ldv;
       double* zwj = Zw + (long long)j * g.P;
-      // z_j = P^{-1} v_j: u and z blocks are v scaled (folded into the matvec), w block stored
-      if (int e = schur_apply(H, vj + 2 * g.P, H->vinv + j, zwj)) return e;
-      // w = K z_j
-      if (int e = launch_kkt_apply(g, vj, vj + g.P, zwj, 1.0 / g.h, 1.0 / (g.omega * g.h), 1.0,
-                                   H->vinv + j, nullptr, w, w + g.P, w + 2 * g.P, s)) return e;
+      // z_j = P^{-1} v_j: u and z blocks are v scaled (folded into the matvec), w block stored;
+      // then w = K z_j
+      auto front = [&]() -> int {
+        if (int e = schur_apply(H, vj + 2 * g.P, H->vinv + j, zwj)) return e;
+        return launch_kkt_apply(g, vj, vj + g.P, zwj, 1.0 / g.h, 1.0 / (g.omega * g.h), 1.0,
+                                H->vinv + j, nullptr, w, w + g.P, w + 2 * g.P, s);
+      };
       if (!dcgs) {
+        if (int e = front()) return e;
         // ---- classical Gram-Schmidt with selective reorthogonalisation ------------------
         const int nv = j + 1;
         double* sums1 = H->ksums;
@@ -1127,12 +1192,16 @@ int fgmres_solve(kktdd_handle* H, const double* f, double* x, int32_t restart, i
       }
       // ---- DCGS2: slot j holds the candidate of v_j, slot j+1 the product W ---------------
       const int ns = 2 * j + 3;
-      if (int e = launch_dcgs_dots(n3, V, ldv, j, vj, w, part, nred, s)) return e;
-      if (int e = launch_reduce_partials(part, nred, ns, sums, s)) return e;
-      if (int e = launch_dcgs_finish(j, sums, H->vinv, H->ydev, rec, H->gate, 1, s)) return e;
-      if (int e = launch_dcgs_update(n3, V, ldv, j, H->ydev, H->gate, part, nred, s)) return e;
-      if (int e = launch_reduce_partials(part, nred, 1, norm_slot, s)) return e;
-      if (int e = launch_dcgs_finish(j, norm_slot, H->vinv, H->ydev, rec, H->gate, 2, s)) return e;
+      auto step_work = [&]() -> int {
+        if (int e = front()) return e;
+        if (int e = launch_dcgs_dots(n3, V, ldv, j, vj, w, part, nred, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, ns, sums, s)) return e;
+        if (int e = launch_dcgs_finish(j, sums, H->vinv, H->ydev, rec, H->gate, 1, s)) return e;
+        if (int e = launch_dcgs_update(n3, V, ldv, j, H->ydev, H->gate, part, nred, s)) return e;
+        if (int e = launch_reduce_partials(part, nred, 1, norm_slot, s)) return e;
+        return launch_dcgs_finish(j, norm_slot, H->vinv, H->ydev, rec, H->gate, 2, s);
+      };
+      if (int e = run_step(H, j, step_work)) return e;
       KKT_HIP(hipMemcpyAsync(H->host_hcol, rec, (2 * j + 5) * sizeof(double), hipMemcpyDeviceToHost, s));
       KKT_HIP(hipStreamSynchronize(s));
       for (int i = 0; i < 2 * j + 5; ++i)

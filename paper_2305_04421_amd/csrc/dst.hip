@@ -39,6 +39,7 @@
 // for the f64 engine and float32 otherwise.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -973,6 +974,7 @@ using TuneKey = std::array<int, 4>;   // kind (0 rows, 1 cols), engine, M, slice
 std::mutex g_tune_mu;
 std::map<TuneKey, Shape> g_tuned;
 bool g_tune_loaded = false;
+std::atomic<int> g_tune_gen{0};   // changes whenever kkt_tune_set replaces a shape
 
 const char* tune_path() {
   const char* p = std::getenv("KKTDD_TUNE_CACHE");
@@ -1011,12 +1013,18 @@ template <> constexpr int engine_id<EngBF<1>>() { return KKTDD_BF16; }
 template <> constexpr int engine_id<EngBF<3>>() { return KKTDD_BF16X3; }
 template <> constexpr int engine_id<EngBF<6>>() { return KKTDD_BF16X6; }
 
-// Dynamic LDS above 64 KiB has to be enabled per kernel before the first launch.
-template <typename F>
-int allow_lds(F* kernel, size_t lds) {
-  if (lds > 65536)
-    KKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+// Dynamic LDS above 64 KiB has to be enabled per kernel before its first launch; the largest
+// size enabled so far is remembered per kernel, so later launches (also those recorded into a
+// HIP graph) make no further runtime call.
+template <auto Kernel>
+int allow_lds(size_t lds) {
+  static std::atomic<size_t> enabled{65536};
+  if (lds <= enabled.load(std::memory_order_acquire)) return 0;
+  KKT_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(Kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  size_t cur = enabled.load();
+  while (lds > cur && !enabled.compare_exchange_weak(cur, lds)) {
+  }
   return 0;
 }
 
@@ -1045,7 +1053,7 @@ int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, i
            hipStream_t s) {
   const size_t lds = Eng::template rows_lds_total<RB>(g.Mx);
   if (lds > kMaxLds) return set_error(KKTDD_EINVAL, "row-kernel shape needs more LDS than a CU has");
-  if (int e = allow_lds(k_rows<Eng, TPW, PD, RB>, lds)) return e;
+  if (int e = allow_lds<k_rows<Eng, TPW, PD, RB>>(lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
   RowArgs<typename Eng::data_t> la = a;
@@ -1064,7 +1072,7 @@ int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, i
   const size_t lds = Eng::template cols_lds_total<CB>(g.My);
   if (lds > kMaxLds || (g.Mx / 16) % CB != 0)
     return set_error(KKTDD_EINVAL, "column-kernel shape does not fit the extent or the LDS");
-  if (int e = allow_lds(k_cols<Eng, TPW, PD, CB>, lds)) return e;
+  if (int e = allow_lds<k_cols<Eng, TPW, PD, CB>>(lds)) return e;
   prof_begin(kclass, s);
   ColArgs<typename Eng::data_t> la = a;
   la.nsl = slice_per_xcd(g, nslices, sizeof(typename Eng::data_t)) ? nslices : 0;
@@ -1494,8 +1502,11 @@ int tune_set(int kind, int precision, int extent, int nslices, int waves, int de
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();
   g_tuned[{kind, precision, extent, nslices}] = Shape{waves, deep, width};
+  g_tune_gen.fetch_add(1);
   return 0;
 }
+
+int tune_generation() { return g_tune_gen.load(); }
 
 int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep, int* width) {
   if (!waves || !deep || !width || extent < 32 || extent % 32 != 0)

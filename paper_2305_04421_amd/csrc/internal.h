@@ -144,6 +144,8 @@ int launch_autotune(const Geom& g, int precision, const void* Sx, const void* Sy
 
 int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep, int width);
 int tune_get(int kind, int precision, int extent, int nslices, int* waves, int* deep, int* width);
+// Counter that kkt_tune_set advances: work recorded with older launch shapes is stale.
+int tune_generation();
 
 int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double* r0,
                           hipStream_t s);
@@ -237,6 +239,10 @@ struct kktdd_handle {
   int elem = 8;                       // bytes per element of the sweep work buffers
   double setup_s = 0.0;               // wall time of kkt_create
   std::vector<double> history;        // residual estimates of the last fgmres_solve
+  // Arnoldi steps recorded as HIP graphs, one per basis slot j (see run_step in api.hip)
+  std::vector<hipGraphExec_t> graph_exec;
+  std::vector<char> graph_ran;         // slot j has run eagerly once (its next run is captured)
+  int graph_gen = 0;                   // tune_generation() the graphs were recorded under
   std::vector<void*> allocations;
 
   // tables: per extent the forward then inverse half-transform blocks (see dst.hip), and
