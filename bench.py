@@ -113,6 +113,8 @@ def parse():
                     help="FGMRES iterations of the CPU oracle sample (0: skip the CPU baseline)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the float32-sweep path")
     ap.add_argument("--no-hoisted", action="store_true", help="skip the transform-hoisted (modal) paths")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven batch of 64 problems measured after the grid512 workload")
     ap.add_argument("--sequential", action="store_true",
                     help="solve the problems of a step one after another instead of as one batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -153,6 +155,7 @@ def main():
         probs.append((name, params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
         del u0, ut
     progress(f"inputs of {len(probs)} problem(s) resident on the device")
+    first_params, first_recipe = probs[0][1], recipes[probs[0][0]]
     unknowns = [3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for _, p, _, _ in probs]
 
     def run_path(precision, steps, warmup, profile, sweep="step", must_converge=True, keep_x=False):
@@ -334,12 +337,76 @@ def main():
         result["hoisted"] = {prec: summary(prec, "modal")
                              for prec in DEFAULT_HOISTED.get(args.workload, ("fp64",) + MIXED)}
 
+    if args.workload == "grid512" and not args.no_batch:
+        # the uneven batch of 64 problems, solved as one batch (float64, and "auto": float32
+        # sweeps where kappa(D_sigma) <= 500), measured after the main workload
+        del probs[:]
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        result["batch_uneven64"] = batch_uneven(args)
+
     if args.cpu_iters > 0:
-        result["cpu_baseline"] = cpu_baseline(args, probs[0][0], probs[0][1], recipes[probs[0][0]],
-                                              st64[0]["iters"])
+        result["cpu_baseline"] = cpu_baseline(args, "grid512" if args.workload == "grid512" else names[0],
+                                              first_params, first_recipe, st64[0]["iters"])
 
     print(json.dumps(result), flush=True)
     return 0
+
+
+def batch_uneven(args):
+    """The uneven batch (64 problems, n in {64..256}, nt 64..512, omega and nu drawn per
+    problem) solved as one kkt_solve_batched call, FGMRES(12) to the same tolerance: float64,
+    and float32 sweeps per problem where kappa(D_sigma) <= 500 ("auto")."""
+    import torch
+    from paper_2305_04421_amd import KKTSolver, solve_batched, workloads as wl
+    dev = torch.device("cuda:0")
+    probs = []
+    for params, recipe in wl.batch_uneven(64, seed=4):
+        u0, ut = wl.data(params, recipe)
+        probs.append((params, torch.from_numpy(u0.reshape(-1)).to(dev), torch.from_numpy(ut.reshape(-1)).to(dev)))
+    unknowns = sum(3 * p["nt"] * (p["nx"] - 1) * (p["ny"] - 1) for p, _, _ in probs)
+    restart = DEFAULT_RESTART["uneven64"]
+    out, ref = {}, None
+    for prec in ("fp64", "auto"):
+        solvers = [KKTSolver(p, prec) for p, _, _ in probs]
+        fs = [S.rhs(u0, ut) for S, (_, u0, ut) in zip(solvers, probs)]
+        xs = [torch.zeros_like(f) for f in fs]
+        for _ in range(args.leg_warmup):
+            for x in xs:
+                x.zero_()
+            solve_batched(solvers, fs, xs, restart=restart, maxit=600, rtol=args.rtol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.leg_steps):
+            for x in xs:
+                x.zero_()
+            _, st = solve_batched(solvers, fs, xs, restart=restart, maxit=600, rtol=args.rtol)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.leg_steps
+        its = [x["iters"] for x in st]
+        leg = {"value": unknowns / dt, "unit": "unknowns/s", "ms_per_step": 1e3 * dt, "steps": args.leg_steps,
+               "warmup": args.leg_warmup, "iterations_sum": sum(its), "iterations_max": max(its),
+               "converged": all(x["status"] == 0 and x["relres_true"] <= args.rtol for x in st),
+               "fp32_sweeps": sum(S.resolved_precision == "fp32" for S in solvers)}
+        if prec == "fp64":
+            ref = ([x.cpu() for x in xs], st)
+        else:
+            errs = sorted(float((x - r.to(dev)).norm() / r.norm()) for x, r in zip(xs, ref[0]))
+            leg["ratio_vs_fp64"] = leg["value"] / out["fp64"]["value"]
+            leg["extra_iterations_max"] = max(a["iters"] - b["iters"] for a, b in zip(st, ref[1]))
+            leg["err_vs_fp64_median"] = errs[len(errs) // 2]
+            leg["err_vs_fp64_max"] = errs[-1]
+            leg["accepted"] = leg["converged"] and all(
+                a["relres_block"][0] <= ACCEPT_U_FACTOR * max(b["relres_block"][0], args.rtol)
+                for a, b in zip(st, ref[1]))
+        progress(f"uneven64 batch {prec}: {leg['ms_per_step']:.1f} ms per step")
+        out[prec] = leg
+        for S in solvers:
+            S.close()
+        del fs, xs
+    out["workload"] = DESCRIPTIONS["uneven64"] + f", FGMRES({restart}) to {args.rtol:g} from x0=0, one batch"
+    out["unknowns_per_step"] = unknowns
+    return out
 
 
 # Above this many KKT unknowns the CPU sample is a time-truncated copy of the problem.
