@@ -31,10 +31,24 @@ k_restrict(Geom g, const double* __restrict__ rw, const double* __restrict__ dsc
   const int s = blockIdx.y;
   if (pt >= g.nxy) return;
   double a0 = 0.0, a1 = 0.0;
-  for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) {
-    const double v = rw[(long long)(n - 1) * g.nxy + pt];
-    a0 += v;
-    a1 += phi1(n, s, g.k) * v;
+  constexpr int kReg = 32;
+  if (g.k <= kReg) {
+    // the subdomain's values are loaded together, then summed in node order
+    double v[kReg];
+#pragma unroll
+    for (int i = 0; i < kReg; ++i) v[i] = i < g.k ? rw[(long long)(s * g.k + i) * g.nxy + pt] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kReg; ++i)
+      if (i < g.k) {
+        a0 += v[i];
+        a1 += phi1(s * g.k + 1 + i, s, g.k) * v[i];
+      }
+  } else {
+    for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) {
+      const double v = rw[(long long)(n - 1) * g.nxy + pt];
+      a0 += v;
+      a1 += phi1(n, s, g.k) * v;
+    }
   }
   const double sc = dscale ? *dscale : 1.0;
   r0[(long long)(g.nb * s) * g.nxy + pt] = sc * a0;

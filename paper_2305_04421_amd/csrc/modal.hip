@@ -45,10 +45,23 @@ k_modal_restrict(Geom g, const T* __restrict__ rhat, double* __restrict__ r0) {
   const int s = blockIdx.y;
   if (m >= MM) return;
   double a0 = 0.0, a1 = 0.0;
-  for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) {
-    const double v = (double)rhat[(long long)(n - 1) * MM + m];
-    a0 += v;
-    a1 += phi1m(n, s, g.k) * v;
+  if (g.k <= kRegSteps) {
+    // the subdomain's values are loaded together, then summed in node order
+    double v[kRegSteps];
+#pragma unroll
+    for (int i = 0; i < kRegSteps; ++i) v[i] = i < g.k ? (double)rhat[(long long)(s * g.k + i) * MM + m] : 0.0;
+#pragma unroll
+    for (int i = 0; i < kRegSteps; ++i)
+      if (i < g.k) {
+        a0 += v[i];
+        a1 += phi1m(s * g.k + 1 + i, s, g.k) * v[i];
+      }
+  } else {
+    for (int n = s * g.k + 1; n <= (s + 1) * g.k; ++n) {
+      const double v = (double)rhat[(long long)(n - 1) * MM + m];
+      a0 += v;
+      a1 += phi1m(n, s, g.k) * v;
+    }
   }
   r0[(long long)(g.nb * s) * MM + m] = a0;
   if (g.nb == 2) r0[(long long)(g.nb * s + 1) * MM + m] = a1;
@@ -134,34 +147,45 @@ k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
   }
   const double d = g.sigma + lamy[q] + lamx[p];
   const double invd = 1.0 / d;
-  double yreg[REG ? kRegSteps : 1];
-  double* ysc = REG ? nullptr : yscratch + ((long long)s * g.L) * MM + m;
+  if constexpr (REG) {
+    // Sweeps of at most kRegSteps nodes: every r'_n of the subdomain is loaded (and corrected
+    // by the coarse part) before the recurrences, so the loads are in flight together; the
+    // one register array then holds y_n, then x_n, which are stored after the adjoint sweep.
+    const int cnt = rg.hi - rg.lo + 1;
+    double v[kRegSteps];
+#pragma unroll
+    for (int i = 0; i < kRegSteps; ++i)
+      v[i] = i < cnt ? rprime_at(g, rhat, c0, sub, d, MM, m, rg.lo + i) : 0.0;
+    double y = 0.0;
+#pragma unroll
+    for (int i = 0; i < kRegSteps; ++i)
+      if (i < cnt) {
+        y = (v[i] + y) * invd;
+        v[i] = y;
+      }
+    double x = 0.0;
+#pragma unroll
+    for (int i = kRegSteps - 1; i >= 0; --i)
+      if (i < cnt) {
+        x = (g.h * v[i] + x) * invd;
+        v[i] = x;
+      }
+#pragma unroll
+    for (int i = 0; i < kRegSteps; ++i)
+      if (i < cnt) put_out(g, rg, c0, MM, m, s, rg.lo + i, v[i], zhat, ext);
+    return;
+  }
+  double* ysc = yscratch + ((long long)s * g.L) * MM + m;
   // forward sweep over the subdomain's nodes (zero state before the first)
   double y = 0.0;
   for (int n = rg.lo; n <= rg.hi; ++n) {
     y = (rprime_at(g, rhat, c0, sub, d, MM, m, n) + y) * invd;
-    const int j = n - rg.first;
-    if (REG) {
-#pragma unroll
-      for (int i = 0; i < kRegSteps; ++i)
-        if (i == j) yreg[i] = y;
-    } else {
-      ysc[(long long)j * MM] = y;
-    }
+    ysc[(long long)(n - rg.first) * MM] = y;
   }
   // adjoint sweep with the mass scale (zero state after the last node)
   double x = 0.0;
   for (int n = rg.hi; n >= rg.lo; --n) {
-    const int j = n - rg.first;
-    double yj = 0.0;
-    if (REG) {
-#pragma unroll
-      for (int i = 0; i < kRegSteps; ++i)
-        if (i == j) yj = yreg[i];
-    } else {
-      yj = ysc[(long long)j * MM];
-    }
-    x = (g.h * yj + x) * invd;
+    x = (g.h * ysc[(long long)(n - rg.first) * MM] + x) * invd;
     put_out(g, rg, c0, MM, m, s, n, x, zhat, ext);
   }
 }
