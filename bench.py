@@ -55,7 +55,7 @@ DEFAULT_RESTART = {"grid512": 12, "uneven64": 12}
 # reduced-precision paths timed per workload (the largest ones time a subset)
 # ("auto": float32 sweeps per problem where kappa(D_sigma) <= 500, else float64)
 DEFAULT_MIXED = {"grid512": ("fp32", "bf16x6", "bf16x3"), "uneven64": ("auto",)}
-DEFAULT_HOISTED = {"grid512": ("fp64", "fp32"), "uneven64": ("fp64", "auto")}
+DEFAULT_HOISTED = {"grid512": ("fp64", "fp32", "bf16x6", "bf16x3"), "uneven64": ("fp64", "auto")}
 # A mixed result counts toward the mixed-vs-float64 ratio only if it meets the same stopping
 # test and leaves its u-block residual within this factor of the float64 solution's: the
 # whole-vector test is dominated by the w block, so a solution can pass it with a loose u block.
@@ -83,12 +83,13 @@ DESCRIPTIONS = {
 }
 # HBM bytes per dispatch from rocprofv3 FETCH_SIZE + WRITE_SIZE (FETCH_SIZE scaled by 2.0,
 # WRITE_SIZE by 1.0: what a 1 GiB device copy reads on those counters), per workload and
-# kernel class, as recorded in profiles/arnoldi_<workload>_fp64_hbm_counters.md for the
-# current kernels.  A class whose kernels changed since the counters were taken, or a
-# workload without counters, is absent (traffic null).
-TRAFFIC = {"grid128": {"arnoldi": 496.85e6, "matvec": 215.83e6},
-           "grid256": {"arnoldi": 8900.26e6, "matvec": 3687.70e6},
-           "grid512": {"arnoldi": 34507.54e6, "matvec": 31325.91e6}}
+# kernel class, as recorded in profiles/sweeps_grid512_hbm_counters.md and
+# profiles/arnoldi_<workload>_fp64_hbm_counters.md for the current kernels.  A class whose
+# kernels changed since the counters were taken, or a workload without counters, is absent
+# (traffic null).
+TRAFFIC = {"grid128": {"arnoldi": 496.85e6},
+           "grid256": {"arnoldi": 8900.26e6},
+           "grid512": {"arnoldi": 34507.54e6, "matvec": 29365.1e6, "sweeps": 1085.44e6}}
 
 
 def progress(msg):
@@ -336,6 +337,11 @@ def main():
         # transform-hoisted Schur block (sine-mode sweeps), measured beside the per-step path
         result["hoisted"] = {prec: summary(prec, "modal")
                              for prec in DEFAULT_HOISTED.get(args.workload, ("fp64",) + MIXED)}
+        ok = {k: v for k, v in result["hoisted"].items() if k != "fp64" and v["accepted"] and v["value"]}
+        if ok:
+            best = max(ok, key=lambda k: ok[k]["value"])
+            result["hoisted_best"] = {"precision": best, "value": ok[best]["value"],
+                                      "ratio_vs_fp64": ok[best]["ratio_vs_fp64"]}
 
     if args.workload == "grid512" and not args.no_batch:
         # the uneven batch of 64 problems, solved as one batch (float64, and "auto": float32
