@@ -150,16 +150,18 @@ size_t kkt_size(const kktdd_handle* h);
 int kkt_precision(const kktdd_handle* h);
 
 /* Launch shapes of the sine-transform GEMM kernels (row kernel: kind 0, column kernel: kind 1)
- * for a padded extent (multiple of 16) and slice count, per precision: waves per workgroup
- * (dividing extent/16, at most 8 tiles per wave), a deep L2 prefetch ring (0/1), and the width:
- * blocks of 16 rows (row kernel) or 16 columns (column kernel) per workgroup, 1, 2 or 4, each
- * table fragment a wave loads serving all of them (width > 1: at most 4 tiles per wave, no
- * deep ring; a width whose workgroup would not fit the LDS, or whose column blocks do not
- * divide the x extent, runs as width 1).  kkt_create measures the candidates on its own
+ * for a padded extent (multiple of 32) and slice count, per precision: waves per workgroup
+ * (even, at most 8, dividing extent/16 with at most 8 tiles per wave; or 16 with at most 2
+ * tiles per wave, width at most 2 and no deep ring), a deep L2 prefetch ring (0/1), and the
+ * width: blocks of 16 rows (row kernel) or 16 columns (column kernel) per workgroup, 1, 2 or
+ * 4, each table fragment a wave loads serving all of them (width > 1: at most 4 tiles per
+ * wave, no deep ring; a width whose workgroup would not fit the LDS, or whose column blocks do
+ * not divide the x extent, runs as width 1).  kkt_create measures the candidates on its own
  * extents and keeps the fastest for the process (disable with KKTDD_AUTOTUNE=0;
- * KKTDD_TUNE_CACHE=<file> keeps them across processes, one JSON object per line).  Every shape performs the same operations in the same order, so results do not
- * depend on it; neither do they on the workgroup placement (one XCD per slice when a launch's
- * slices take at most 8 MiB, else slices spread over the XCDs; KKTDD_XCD_MAP=0|1 forces it).
+ * KKTDD_TUNE_CACHE=<file> keeps them across processes, one JSON object per line).  Every
+ * shape performs the same operations in the same order, so results do not depend on it;
+ * neither do they on the workgroup placement (one XCD per slice when a launch's slices take
+ * at most 8 MiB, else slices spread over the XCDs; KKTDD_XCD_MAP=0|1 forces it).
  * Host-only; set returns KKTDD_EINVAL for an invalid shape. */
 int kkt_tune_set(int32_t kind, int32_t precision, int32_t extent, int32_t nslices, int32_t waves,
                  int32_t deep, int32_t width);

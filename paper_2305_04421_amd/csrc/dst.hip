@@ -82,6 +82,24 @@ constexpr int kPDDefault = 4;
 template <int TPW>
 constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
 
+// Workgroup size bound of a kernel: those with at most two tiles per wave and at most two
+// blocks per workgroup (all within 128 VGPRs) also run as 16-wave workgroups, which fill a CU
+// alone; the others take at most 8 waves.
+template <int TPW, int PD, int W>
+constexpr int max_threads() { return (TPW <= 2 && W <= 2 && PD == kPDDefault) ? 1024 : 512; }
+
+// A launch shape for t tiles per transformed extent: nw waves (even, dividing t, at most 8
+// tiles each; 16 only with at most two tiles each and at most two blocks), the default or the
+// deep ring, 1, 2 or 4 blocks per workgroup (several blocks: at most 4 tiles per wave, default
+// ring).
+inline bool shape_valid(int t, int nw, int deep, int width) {
+  if (nw < 2 || (nw & 1) || t % nw != 0 || t / nw > 8) return false;
+  if (deep < 0 || deep > 1 || (width != 1 && width != 2 && width != 4)) return false;
+  if (width > 1 && (deep || t / nw > 4)) return false;
+  if (nw > 8 && (nw != 16 || t / nw > 2 || width > 2 || deep)) return false;
+  return true;
+}
+
 // ---- plain engines (f64, f32) ----------------------------------------------------------
 // A half-transform table Q holds two H x H blocks (H = M/2), block b at Q + b*H*H, its rows
 // stored in k-step groups (see the table loads below).
@@ -586,7 +604,7 @@ __device__ inline const typename Eng::s_t* table(const void* S, int M, int inver
 // loads and stores overlap the other's MFMAs), and the right-hand-side operands are fetched
 // after the first product instead of before it.
 template <typename Eng, int TPW, int PD, int RB>
-__global__ void __launch_bounds__(512, (Eng::template two_per_cu<TPW, PD, RB>() ? 4 : 1))
+__global__ void __launch_bounds__((max_threads<TPW, PD, RB>()), (Eng::template two_per_cu<TPW, PD, RB>() ? 4 : 1))
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
@@ -812,7 +830,7 @@ struct ColArgs {
 };
 
 template <typename Eng, int TPW, int PD, int CB>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__((max_threads<TPW, PD, CB>()))
 k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
@@ -1053,6 +1071,7 @@ int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, i
            hipStream_t s) {
   const size_t lds = Eng::template rows_lds_total<RB>(g.Mx);
   if (lds > kMaxLds) return set_error(KKTDD_EINVAL, "row-kernel shape needs more LDS than a CU has");
+  if (64 * nw > max_threads<TPW, PD, RB>()) return set_error(KKTDD_EINVAL, "row-kernel shape has too many waves");
   if (int e = allow_lds<k_rows<Eng, TPW, PD, RB>>(lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
@@ -1070,8 +1089,8 @@ template <typename Eng, int TPW, int PD, int CB>
 int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
   const size_t lds = Eng::template cols_lds_total<CB>(g.My);
-  if (lds > kMaxLds || (g.Mx / 16) % CB != 0)
-    return set_error(KKTDD_EINVAL, "column-kernel shape does not fit the extent or the LDS");
+  if (lds > kMaxLds || (g.Mx / 16) % CB != 0 || 64 * nw > max_threads<TPW, PD, CB>())
+    return set_error(KKTDD_EINVAL, "column-kernel shape does not fit the extent, the LDS or the waves");
   if (int e = allow_lds<k_cols<Eng, TPW, PD, CB>>(lds)) return e;
   prof_begin(kclass, s);
   ColArgs<typename Eng::data_t> la = a;
@@ -1359,9 +1378,8 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     cand[nc++] = Shape{waves_for(M), 0, 1};
     for (int width : {1, 2, 4}) {
       if (!width_fits<Eng>(kind, g, width)) continue;
-      for (int nw : {waves_for(M), 2, 4, 8, t}) {
-        if (nw < 2 || nw > 8 || (nw & 1) || t % nw != 0 || t / nw > 8) continue;
-        if (width > 1 && t / nw > 4) continue;
+      for (int nw : {waves_for(M), 2, 4, 8, 16, t}) {
+        if (!shape_valid(t, nw, 0, width)) continue;
         bool seen = false;
         for (int i = 0; i < nc; ++i) seen = seen || (cand[i].nw == nw && cand[i].width == width);
         if (!seen && nc < 32) cand[nc++] = Shape{nw, 0, width};
@@ -1495,9 +1513,7 @@ namespace kktdd {
 int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep, int width) {
   const int t = extent / 16;
   if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 32 ||
-      extent % 32 != 0 || nslices < 1 || waves < 2 || waves > 8 || (waves & 1) || t % waves != 0 ||
-      t / waves > 8 || deep < 0 || deep > 1 || (width != 1 && width != 2 && width != 4) ||
-      (width > 1 && (deep || t / waves > 4)))
+      extent % 32 != 0 || nslices < 1 || !shape_valid(t, waves, deep, width))
     return set_error(KKTDD_EINVAL, "invalid launch shape");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();

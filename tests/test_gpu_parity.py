@@ -168,19 +168,31 @@ def test_launch_shapes_give_identical_results(name, precision, sweep):
             assert torch.equal(z, ref), shapes
 
 
+# (nx, ny) -> padded extents (rows, cols) and the shape pairs tried there; 16-wave workgroups
+# (two tiles per wave) exist where an extent has a multiple of 16 tiles (512 here)
+WIDTH_GEOMETRIES = {
+    (385, 512): ((384, 512), [((8, 0, 1), (8, 0, 1)), ((8, 0, 2), (8, 0, 2)), ((8, 0, 4), (8, 0, 4)),
+                              ((8, 0, 2), (8, 0, 1)), ((8, 0, 2), (16, 0, 2)), ((8, 0, 1), (16, 0, 1))]),
+    (512, 385): ((512, 384), [((8, 0, 1), (8, 0, 1)), ((16, 0, 2), (8, 0, 2)), ((16, 0, 1), (8, 0, 4))]),
+}
+
+
+@pytest.mark.parametrize("geometry", list(WIDTH_GEOMETRIES))
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x6", "bf16x3", "bf16"])
-def test_block_widths_give_identical_results_at_the_largest_extents(precision):
-    """The spatial solve at padded extents 384 x 512 (three and four tiles per wave, every
-    grid512 sweep launch) under each workgroup width: bitwise equal to one block per group."""
+def test_block_widths_give_identical_results_at_the_largest_extents(precision, geometry):
+    """The spatial solve at padded extents 384 and 512 (three and four tiles per wave at 8
+    waves, every grid512 sweep launch; two tiles per wave at 16 waves) under each workgroup
+    width and wave count: bitwise equal to one block per 8-wave group."""
     from paper_2305_04421_amd import _lib
     lib = _lib.load()
-    params = wl.problem(nx=385, ny=512, nt=4, Lx=1.0, Ly=1.7, nu=0.05, omega=1e-3, n_sub=1, overlap=0, coarse=0)
+    nx, ny = geometry
+    extents, pairs = WIDTH_GEOMETRIES[geometry]
+    params = wl.problem(nx=nx, ny=ny, nt=4, Lx=1.0, Ly=1.7, nu=0.05, omega=1e-3, n_sub=1, overlap=0, coarse=0)
     p = Problem(**params).validate()
     b = dev(wl.random_field((3,) + p.slice_shape, 108))
     prec = _lib.PRECISIONS[precision]
-    pairs = [((8, 0, 1), (8, 0, 1)), ((8, 0, 2), (8, 0, 2)), ((8, 0, 4), (8, 0, 4)), ((8, 0, 2), (8, 0, 1))]
     with solver(params, precision) as S:
-        out = _shape_sweep(lib, prec, (384, 512), 3, lambda: S.spatial_solve(b, 1.3).clone(), pairs)
+        out = _shape_sweep(lib, prec, extents, 3, lambda: S.spatial_solve(b, 1.3).clone(), pairs)
     ref = out[0][1]
     for shapes, x in out[1:]:
         assert torch.equal(x, ref), shapes
