@@ -152,7 +152,8 @@ int kkt_precision(const kktdd_handle* h);
 /* Launch shapes of the sine-transform GEMM kernels (row kernel: kind 0, column kernel: kind 1)
  * for a padded extent (multiple of 32) and slice count, per precision: waves per workgroup
  * (even, at most 8, dividing extent/16 with at most 8 tiles per wave; or 16 with at most 2
- * tiles per wave, width at most 2 and no deep ring), a deep L2 prefetch ring (0/1), and the
+ * tiles per wave, no deep ring and a width of at most 2 for KKTDD_FP64 and KKTDD_BF16X6, at
+ * most 4 for the other precisions), a deep L2 prefetch ring (0/1), and the
  * width: blocks of 16 rows (row kernel) or 16 columns (column kernel) per workgroup, 1, 2 or
  * 4, each table fragment a wave loads serving all of them (width > 1: at most 4 tiles per
  * wave, no deep ring; a width whose workgroup would not fit the LDS, or whose column blocks do

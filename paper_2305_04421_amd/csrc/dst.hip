@@ -82,21 +82,21 @@ constexpr int kPDDefault = 4;
 template <int TPW>
 constexpr int deep_prefetch() { return TPW == 1 ? 16 : (TPW <= 4 ? 8 : kPDDefault); }
 
-// Workgroup size bound of a kernel: those with at most two tiles per wave and at most two
-// blocks per workgroup (all within 128 VGPRs) also run as 16-wave workgroups, which fill a CU
-// alone; the others take at most 8 waves.
-template <int TPW, int PD, int W>
-constexpr int max_threads() { return (TPW <= 2 && W <= 2 && PD == kPDDefault) ? 1024 : 512; }
+// Workgroup size bound of a kernel: those with at most two tiles per wave and at most
+// Eng::kMaxW16 blocks per workgroup (the kernels that stay within 128 VGPRs) also run as
+// 16-wave workgroups, which fill a CU alone; the others take at most 8 waves.
+template <typename Eng, int TPW, int PD, int W>
+constexpr int max_threads() { return (TPW <= 2 && W <= Eng::kMaxW16 && PD == kPDDefault) ? 1024 : 512; }
 
 // A launch shape for t tiles per transformed extent: nw waves (even, dividing t, at most 8
-// tiles each; 16 only with at most two tiles each and at most two blocks), the default or the
-// deep ring, 1, 2 or 4 blocks per workgroup (several blocks: at most 4 tiles per wave, default
-// ring).
-inline bool shape_valid(int t, int nw, int deep, int width) {
+// tiles each; 16 only with at most two tiles each and at most max_w16 blocks), the default or
+// the deep ring, 1, 2 or 4 blocks per workgroup (several blocks: at most 4 tiles per wave,
+// default ring).
+inline bool shape_valid(int t, int nw, int deep, int width, int max_w16) {
   if (nw < 2 || (nw & 1) || t % nw != 0 || t / nw > 8) return false;
   if (deep < 0 || deep > 1 || (width != 1 && width != 2 && width != 4)) return false;
   if (width > 1 && (deep || t / nw > 4)) return false;
-  if (nw > 8 && (nw != 16 || t / nw > 2 || width > 2 || deep)) return false;
+  if (nw > 8 && (nw != 16 || t / nw > 2 || width > max_w16 || deep)) return false;
   return true;
 }
 
@@ -117,6 +117,7 @@ struct EngPlain {
   using acc_t = typename AccT<T>::type;
   using s_t = T;
   static constexpr int kTableParts = 1;
+  static constexpr int kMaxW16 = sizeof(T) == 8 ? 2 : 4;   // blocks of a 16-wave workgroup
   template <int W> static __host__ __device__ size_t rows_lds(int M) { return (size_t)16 * W * (M + 1) * sizeof(T); }
   template <int W> static __host__ __device__ size_t cols_lds(int M) { return (size_t)M * (16 * W + 1) * sizeof(T); }
   // The combine buffer of the inverse products is the operand buffer itself, in the same
@@ -387,6 +388,7 @@ struct EngBF {
   using acc_t = v4f;
   using s_t = __bf16;
   static constexpr int kTableParts = 3;
+  static constexpr int kMaxW16 = NP <= 2 ? 4 : 2;          // blocks of a 16-wave workgroup
   template <int W> static __host__ __device__ size_t rows_lds(int M) { return (size_t)NP * 16 * W * (M + 8) * 2; }
   template <int W> static __host__ __device__ size_t cols_lds(int M) { return (size_t)NP * 16 * W * (M + 8) * 2; }
   // The float combine buffers ([16W][M+1] rows, [M][16W+1] cols) overlap the operand parts, so
@@ -604,7 +606,7 @@ __device__ inline const typename Eng::s_t* table(const void* S, int M, int inver
 // loads and stores overlap the other's MFMAs), and the right-hand-side operands are fetched
 // after the first product instead of before it.
 template <typename Eng, int TPW, int PD, int RB>
-__global__ void __launch_bounds__((max_threads<TPW, PD, RB>()), (Eng::template two_per_cu<TPW, PD, RB>() ? 4 : 1))
+__global__ void __launch_bounds__((max_threads<Eng, TPW, PD, RB>()), (Eng::template two_per_cu<TPW, PD, RB>() ? 4 : 1))
 k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
@@ -830,7 +832,7 @@ struct ColArgs {
 };
 
 template <typename Eng, int TPW, int PD, int CB>
-__global__ void __launch_bounds__((max_threads<TPW, PD, CB>()))
+__global__ void __launch_bounds__((max_threads<Eng, TPW, PD, CB>()))
 k_cols(Geom g, ColArgs<typename Eng::data_t> a) {
   using T = typename Eng::data_t;
   using acc_t = typename Eng::acc_t;
@@ -1071,7 +1073,7 @@ int rows_t(const Geom& g, const RowArgs<typename Eng::data_t>& a, int nslices, i
            hipStream_t s) {
   const size_t lds = Eng::template rows_lds_total<RB>(g.Mx);
   if (lds > kMaxLds) return set_error(KKTDD_EINVAL, "row-kernel shape needs more LDS than a CU has");
-  if (64 * nw > max_threads<TPW, PD, RB>()) return set_error(KKTDD_EINVAL, "row-kernel shape has too many waves");
+  if (64 * nw > max_threads<Eng, TPW, PD, RB>()) return set_error(KKTDD_EINVAL, "row-kernel shape has too many waves");
   if (int e = allow_lds<k_rows<Eng, TPW, PD, RB>>(lds)) return e;
   const int ngemm = (a.g1_in ? 1 : 0) + (a.b_mode != B_NONE ? 1 : 0);
   prof_begin(kclass, s);
@@ -1089,7 +1091,7 @@ template <typename Eng, int TPW, int PD, int CB>
 int cols_t(const Geom& g, const ColArgs<typename Eng::data_t>& a, int nslices, int nw, int kclass,
            hipStream_t s) {
   const size_t lds = Eng::template cols_lds_total<CB>(g.My);
-  if (lds > kMaxLds || (g.Mx / 16) % CB != 0 || 64 * nw > max_threads<TPW, PD, CB>())
+  if (lds > kMaxLds || (g.Mx / 16) % CB != 0 || 64 * nw > max_threads<Eng, TPW, PD, CB>())
     return set_error(KKTDD_EINVAL, "column-kernel shape does not fit the extent, the LDS or the waves");
   if (int e = allow_lds<k_cols<Eng, TPW, PD, CB>>(lds)) return e;
   prof_begin(kclass, s);
@@ -1379,7 +1381,7 @@ int autotune_t(const Geom& g, const void* Sx, const void* Sy, const void* invlam
     for (int width : {1, 2, 4}) {
       if (!width_fits<Eng>(kind, g, width)) continue;
       for (int nw : {waves_for(M), 2, 4, 8, 16, t}) {
-        if (!shape_valid(t, nw, 0, width)) continue;
+        if (!shape_valid(t, nw, 0, width, Eng::kMaxW16)) continue;
         bool seen = false;
         for (int i = 0; i < nc; ++i) seen = seen || (cand[i].nw == nw && cand[i].width == width);
         if (!seen && nc < 32) cand[nc++] = Shape{nw, 0, width};
@@ -1510,10 +1512,21 @@ int launch_coarse_idst(const Geom& g, const double* Sx, const double* Sy, const 
 
 namespace kktdd {
 
+// Blocks a 16-wave workgroup of an engine may hold.
+static int max_w16_for(int precision) {
+  switch (precision) {
+    case KKTDD_FP64: return EngPlain<double>::kMaxW16;
+    case KKTDD_FP32: return EngPlain<float>::kMaxW16;
+    case KKTDD_BF16: return EngBF<1>::kMaxW16;
+    case KKTDD_BF16X3: return EngBF<3>::kMaxW16;
+    default: return EngBF<6>::kMaxW16;
+  }
+}
+
 int tune_set(int kind, int precision, int extent, int nslices, int waves, int deep, int width) {
   const int t = extent / 16;
   if (kind < 0 || kind > 1 || precision < KKTDD_FP64 || precision > KKTDD_BF16X6 || extent < 32 ||
-      extent % 32 != 0 || nslices < 1 || !shape_valid(t, waves, deep, width))
+      extent % 32 != 0 || nslices < 1 || !shape_valid(t, waves, deep, width, max_w16_for(precision)))
     return set_error(KKTDD_EINVAL, "invalid launch shape");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   tune_load_locked();

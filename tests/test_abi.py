@@ -153,15 +153,20 @@ def test_launch_shape_table(lib):
     assert lib.kkt_tune_get(1, _lib.FP64, 512, 7, ctypes.byref(w), ctypes.byref(d), ctypes.byref(b)) == 0
     assert (w.value, d.value, b.value) == (16, 0, 2)
     assert lib.kkt_tune_set(0, _lib.BF16X6, 256, 7, 16, 0, 1) == 0
+    # four blocks in 16 waves where the two-tile kernels fit: not float64 or bf16x6
+    assert lib.kkt_tune_set(0, _lib.BF16X3, 512, 7, 16, 0, 4) == 0
+    assert lib.kkt_tune_set(1, _lib.FP32, 512, 7, 16, 0, 4) == 0
+    assert lib.kkt_tune_set(0, _lib.FP64, 512, 7, 16, 0, 4) == _lib.EINVAL
+    assert lib.kkt_tune_set(0, _lib.BF16X6, 512, 7, 16, 0, 4) == _lib.EINVAL
     # wave counts must be even (each wave stays inside one half of the folded transform),
     # extents multiples of 32, at most 8 tiles per wave; widths 1, 2 or 4, and a width above 1
     # takes the shallow ring and at most 4 tiles per wave; more than 8 waves only as 16 waves
-    # of at most two tiles and at most two blocks, with the shallow ring
+    # of at most two tiles with the shallow ring
     for bad in [(2, 0, 128, 4, 8, 0, 1), (0, 9, 128, 4, 8, 0, 1), (0, 0, 100, 4, 4, 0, 1),
                 (0, 0, 128, 4, 3, 0, 1), (0, 0, 128, 4, 1, 0, 1), (0, 0, 16, 4, 2, 0, 1),
                 (0, 0, 512, 4, 2, 0, 1), (0, 0, 128, 0, 8, 0, 1), (0, 0, 128, 4, 8, 2, 1),
                 (0, 0, 128, 4, 8, 0, 3), (0, 0, 128, 4, 8, 1, 2), (0, 0, 512, 4, 4, 0, 2),
-                (0, 0, 128, 4, 8, 0, 0), (0, 0, 768, 4, 16, 0, 1), (0, 0, 512, 4, 16, 0, 4),
+                (0, 0, 128, 4, 8, 0, 0), (0, 0, 768, 4, 16, 0, 1), (0, 0, 512, 4, 16, 0, 8),
                 (0, 0, 512, 4, 16, 1, 1), (0, 0, 512, 4, 12, 0, 1), (0, 0, 1024, 4, 32, 0, 1),
                 (0, 0, 384, 4, 16, 0, 1)]:
         assert lib.kkt_tune_set(*bad) == _lib.EINVAL, bad

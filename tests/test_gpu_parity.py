@@ -175,6 +175,8 @@ WIDTH_GEOMETRIES = {
                               ((8, 0, 2), (8, 0, 1)), ((8, 0, 2), (16, 0, 2)), ((8, 0, 1), (16, 0, 1))]),
     (512, 385): ((512, 384), [((8, 0, 1), (8, 0, 1)), ((16, 0, 2), (8, 0, 2)), ((16, 0, 1), (8, 0, 4))]),
 }
+# 16-wave workgroups of four blocks: the engines whose two-tile kernels fit them
+WIDTH_PAIRS_16x4 = {(385, 512): [((8, 0, 4), (16, 0, 4))], (512, 385): [((16, 0, 4), (8, 0, 2))]}
 
 
 @pytest.mark.parametrize("geometry", list(WIDTH_GEOMETRIES))
@@ -187,6 +189,8 @@ def test_block_widths_give_identical_results_at_the_largest_extents(precision, g
     lib = _lib.load()
     nx, ny = geometry
     extents, pairs = WIDTH_GEOMETRIES[geometry]
+    if precision in ("fp32", "bf16x3", "bf16"):
+        pairs = pairs + WIDTH_PAIRS_16x4[geometry]
     params = wl.problem(nx=nx, ny=ny, nt=4, Lx=1.0, Ly=1.7, nu=0.05, omega=1e-3, n_sub=1, overlap=0, coarse=0)
     p = Problem(**params).validate()
     b = dev(wl.random_field((3,) + p.slice_shape, 108))
