@@ -165,38 +165,45 @@ struct EngPlain {
     T2 bq[RP][TPW];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
-      if (p < npr) {
-        const T2* Qk = Qb + (long long)(4 * p) * H;
+      {   // every ring slot filled (a short extent repeats the last pair): all loads are counted
+        const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
       }
-    for (int pr0 = 0; pr0 < npr; pr0 += RP) {
+    // one ring step: slot p holds the table operands of k-step pair pr
+    auto step = [&](const int p, const int pr) __attribute__((always_inline)) {
+      T a0[W], a1[W];
 #pragma unroll
-      for (int p = 0; p < RP; ++p) {
-        const int pr = pr0 + p;
-        if (pr >= npr) break;
-        T a0[W], a1[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          a0[w] = Ab[w * ldr + 8 * pr];
-          a1[w] = Ab[w * ldr + 8 * pr + 4];
-        }
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a0[w], bq[p][t].x, acc[w][t]);
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a1[w], bq[p][t].y, acc[w][t]);
-        const int kn = pr + RP;
-        if (kn < npr) {
-          const T2* Qk = Qb + (long long)(4 * kn) * H;
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
-        }
+      for (int w = 0; w < W; ++w) {
+        a0[w] = Ab[w * ldr + 8 * pr];
+        a1[w] = Ab[w * ldr + 8 * pr + 4];
       }
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a0[w], bq[p][t].x, acc[w][t]);
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(a1[w], bq[p][t].y, acc[w][t]);
+      // refilled on every step (past the end with the last pair again: in bounds, never used)
+      const int kn = pr + RP < npr ? pr + RP : npr - 1;
+      {
+        const T2* Qk = Qb + (long long)(4 * kn) * H;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
+      }
+    };
+    // whole ring rounds, then the pairs left over: with no exit inside a round the compiler
+    // counts the refills in flight instead of draining the ring on every round
+    int pr0 = 0;
+    for (; pr0 + RP <= npr; pr0 += RP) {
+#pragma unroll
+      for (int p = 0; p < RP; ++p) step(p, pr0 + p);
     }
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+      if (pr0 + p < npr) step(p, pr0 + p);
   }
   template <int TPW, int kPD, int W>
   static __device__ void gemm_left2(const T* __restrict__ Q, const unsigned char* lds, int M,
@@ -212,38 +219,45 @@ struct EngPlain {
     T2 aq[RP][TPW];
 #pragma unroll
     for (int p = 0; p < RP; ++p)
-      if (p < npr) {
-        const T2* Qk = Qb + (long long)(4 * p) * H;
+      {   // every ring slot filled (a short extent repeats the last pair): all loads are counted
+        const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
 #pragma unroll
         for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
       }
-    for (int pr0 = 0; pr0 < npr; pr0 += RP) {
+    // one ring step: slot p holds the table operands of k-step pair pr
+    auto step = [&](const int p, const int pr) __attribute__((always_inline)) {
+      T b0[W], b1[W];
 #pragma unroll
-      for (int p = 0; p < RP; ++p) {
-        const int pr = pr0 + p;
-        if (pr >= npr) break;
-        T b0[W], b1[W];
-#pragma unroll
-        for (int w = 0; w < W; ++w) {
-          b0[w] = Bb[8 * pr * ldb + 16 * w];
-          b1[w] = Bb[(8 * pr + 4) * ldb + 16 * w];
-        }
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].x, b0[w], acc[w][t]);
-#pragma unroll
-        for (int w = 0; w < W; ++w)
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].y, b1[w], acc[w][t]);
-        const int kn = pr + RP;
-        if (kn < npr) {
-          const T2* Qk = Qb + (long long)(4 * kn) * H;
-#pragma unroll
-          for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
-        }
+      for (int w = 0; w < W; ++w) {
+        b0[w] = Bb[8 * pr * ldb + 16 * w];
+        b1[w] = Bb[(8 * pr + 4) * ldb + 16 * w];
       }
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].x, b0[w], acc[w][t]);
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) acc[w][t] = mfma16(aq[p][t].y, b1[w], acc[w][t]);
+      // refilled on every step (past the end with the last pair again: in bounds, never used)
+      const int kn = pr + RP < npr ? pr + RP : npr - 1;
+      {
+        const T2* Qk = Qb + (long long)(4 * kn) * H;
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
+      }
+    };
+    // whole ring rounds, then the pairs left over: with no exit inside a round the compiler
+    // counts the refills in flight instead of draining the ring on every round
+    int pr0 = 0;
+    for (; pr0 + RP <= npr; pr0 += RP) {
+#pragma unroll
+      for (int p = 0; p < RP; ++p) step(p, pr0 + p);
     }
+#pragma unroll
+    for (int p = 0; p < RP; ++p)
+      if (pr0 + p < npr) step(p, pr0 + p);
   }
   // float32: k-steps in groups of four, one 16-byte load per lane brings four of them.
   template <int TPW, int kPD, int W>
