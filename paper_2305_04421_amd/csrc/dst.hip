@@ -163,13 +163,13 @@ struct EngPlain {
     const int npr = H >> 3;           // k-step pairs
     constexpr int RP = kPD / 2;       // ring depth in pairs
     T2 bq[RP][TPW];
+    // every ring slot is filled (a short extent repeats its last pair), so all loads are counted
 #pragma unroll
-    for (int p = 0; p < RP; ++p)
-      {   // every ring slot filled (a short extent repeats the last pair): all loads are counted
-        const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
+    for (int p = 0; p < RP; ++p) {
+      const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
-      }
+      for (int t = 0; t < TPW; ++t) bq[p][t] = Qk[voff[t]];
+    }
     // one ring step: slot p holds the table operands of k-step pair pr
     auto step = [&](const int p, const int pr) __attribute__((always_inline)) {
       T a0[W], a1[W];
@@ -217,13 +217,13 @@ struct EngPlain {
     const int npr = H >> 3;
     constexpr int RP = kPD / 2;
     T2 aq[RP][TPW];
+    // every ring slot is filled (a short extent repeats its last pair), so all loads are counted
 #pragma unroll
-    for (int p = 0; p < RP; ++p)
-      {   // every ring slot filled (a short extent repeats the last pair): all loads are counted
-        const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
+    for (int p = 0; p < RP; ++p) {
+      const T2* Qk = Qb + (long long)(4 * (p < npr ? p : npr - 1)) * H;
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
-      }
+      for (int t = 0; t < TPW; ++t) aq[p][t] = Qk[voff[t]];
+    }
     // one ring step: slot p holds the table operands of k-step pair pr
     auto step = [&](const int p, const int pr) __attribute__((always_inline)) {
       T b0[W], b1[W];
