@@ -36,8 +36,10 @@ __device__ inline double phi1m(int node, int s, int k) {
   return -1.0 + 2.0 * (double)(node - s * k) / (double)k;
 }
 
-// coarse restriction in mode space: r0[nb*s + b][q*Mx + p] (float64, padded layout)
-template <typename T>
+// coarse restriction in mode space: r0[nb*s + b][q*Mx + p] (float64, padded layout).  With
+// k <= R the subdomain's values are loaded together (unconditionally, the node index clamped
+// to the last owned node; entries past k are not used), then summed in node order.
+template <typename T, int R>
 __global__ void __launch_bounds__(kBlock)
 k_modal_restrict(Geom g, const T* __restrict__ rhat, double* __restrict__ r0) {
   const long long MM = g.padded();
@@ -45,13 +47,13 @@ k_modal_restrict(Geom g, const T* __restrict__ rhat, double* __restrict__ r0) {
   const int s = blockIdx.y;
   if (m >= MM) return;
   double a0 = 0.0, a1 = 0.0;
-  if (g.k <= kRegSteps) {
-    // the subdomain's values are loaded together, then summed in node order
-    double v[kRegSteps];
+  if (R > 0) {
+    double v[R > 0 ? R : 1];
 #pragma unroll
-    for (int i = 0; i < kRegSteps; ++i) v[i] = i < g.k ? (double)rhat[(long long)(s * g.k + i) * MM + m] : 0.0;
+    for (int i = 0; i < R; ++i)
+      v[i] = (double)rhat[(long long)(s * g.k + (i < g.k ? i : g.k - 1)) * MM + m];
 #pragma unroll
-    for (int i = 0; i < kRegSteps; ++i)
+    for (int i = 0; i < R; ++i)
       if (i < g.k) {
         a0 += v[i];
         a1 += phi1m(s * g.k + 1 + i, s, g.k) * v[i];
@@ -128,9 +130,130 @@ __device__ inline void put_out(const Geom& g, const Range& rg, const double* __r
   }
 }
 
+// Lane i of a wave reads the value that lane `lane` holds (wave-uniform result).
+__device__ inline double lane_value(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+template <int W>
+__device__ inline double pick(const double (&a)[W], int j) {
+  double r = a[0];
+#pragma unroll
+  for (int t = 1; t < W; ++t) r = j == t ? a[t] : r;
+  return r;
+}
+
+// One thread = one sine mode of one subdomain whose sweep covers at most R nodes: residual,
+// forward sweep, adjoint sweep, output, with the states in registers.  Every load is issued
+// before any arithmetic and none sits under a branch, so they are all in flight together:
+//   - R values of r_hat, the node index clamped to the sweep's last node (entries past the
+//     sweep are loaded but not used);
+//   - with the coarse level (W > 0), the coarse values of the W subdomains s-W/2 .. s+W/2
+//     (clamped to 0..nd-1), which own every node lo-1 .. hi+1 the residual and the output read:
+//     W = 3 when delta < k, 5 when delta = k.
+// The owner slot and linear basis value of node lo-1+i sit in lane i of every wave (all lanes
+// active) and are read back as wave-uniform values, so c_hat of a node is one select chain
+// and one multiply-add.  `sub` subtracts S_hat c_hat / h from r_hat (coarse level first);
+// with W > 0 the output adds c_hat on owned nodes either way.  Padded modes compute on an
+// in-range eigenvalue entry and write zeros.  The padded mode count is a multiple of the
+// workgroup size, so every thread has a mode.
+template <typename T, int R, int W>
+__global__ void __launch_bounds__(kBlock)
+k_modal_sweep_reg(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0, int sub,
+                  const double* __restrict__ lamx, const double* __restrict__ lamy,
+                  T* __restrict__ zhat, double* __restrict__ ext) {
+  static_assert(R + 2 <= 64, "the node table needs a lane per node");
+  const long long MM = g.padded();
+  const long long m = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const int s = blockIdx.y;
+  const Range rg = node_range(g, s);
+  const int cnt = rg.hi - rg.lo + 1;
+  int tslot = -1;
+  double tphi = 0.0;
+  if constexpr (W > 0) {
+    const int node = rg.lo - 1 + (int)__lane_id();
+    if (node >= 1 && node <= g.nt) {
+      const int o = (node - 1) / g.k;
+      tslot = o - s + W / 2;
+      if (g.nb == 2) tphi = phi1m(node, o, g.k);
+    }
+  }
+  const int q = mode_at((int)(m / g.Mx), g.My), p = mode_at((int)(m % g.Mx), g.Mx);
+  const bool pad = q >= g.my || p >= g.mx;
+  const double d = g.sigma + lamy[pad ? 0 : q] + lamx[pad ? 0 : p];
+  const double invd = 1.0 / d;
+  double v[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    v[i] = (double)rhat[(long long)(rg.lo - 1 + (i < cnt ? i : cnt - 1)) * MM + m];
+  double ch[R + 2];
+  if constexpr (W > 0) {
+    double ca[W], cb[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      int o = s - W / 2 + j;
+      o = o < 0 ? 0 : (o >= g.nd ? g.nd - 1 : o);
+      ca[j] = c0[(long long)(g.nb * o) * MM + m];
+      cb[j] = c0[(long long)(g.nb * o + g.nb - 1) * MM + m];
+    }
+    const bool lin = g.nb == 2;
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) {
+      const int j = __builtin_amdgcn_readlane(tslot, i);
+      const double ph = lane_value(tphi, i);
+      const double a = pick<W>(ca, j);
+      const double c = lin ? a + ph * pick<W>(cb, j) : a;
+      ch[i] = j < 0 ? 0.0 : c;
+    }
+    if (sub) {
+#pragma unroll
+      for (int i = 0; i < R; ++i)
+        if (i < cnt) {
+          // (S_hat c)^n h = (d^2 + [n>=2]) c^n - d c^{n+1} - [n>=2] d c^{n-1}, n = lo + i
+          const double cn = ch[i + 1];
+          double sc = d * d * cn - d * ch[i + 2];
+          if (rg.lo + i >= 2) sc += cn - d * ch[i];
+          v[i] -= sc / g.h;
+        }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < R + 2; ++i) ch[i] = 0.0;
+  }
+  double y = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if (i < cnt) {
+      y = (v[i] + y) * invd;
+      v[i] = y;
+    }
+  double x = 0.0;
+#pragma unroll
+  for (int i = R - 1; i >= 0; --i)
+    if (i < cnt) {
+      x = (g.h * v[i] + x) * invd;
+      v[i] = x;
+    }
+  const int E = g.delta * (1 + g.sym);
+#pragma unroll
+  for (int i = 0; i < R; ++i)
+    if (i < cnt) {
+      const int n = rg.lo + i;
+      if (n >= rg.own_lo && n <= rg.own_hi) {
+        zhat[(long long)(n - 1) * MM + m] = pad ? (T)0 : (T)(ch[i + 1] + v[i]);
+      } else if (ext && !pad) {
+        const int slot = n < rg.own_lo ? n - rg.first : g.delta + (n - rg.own_hi - 1);
+        ext[((long long)s * E + slot) * MM + m] = v[i];
+      }
+    }
+}
+
 // One thread = one sine mode of one subdomain: residual, forward sweep, adjoint sweep,
-// output.  Padded modes write zeros on their owned nodes.
-template <typename T, bool REG>
+// output, for sweeps longer than the register form takes; the forward states go to a
+// float64 store.  Padded modes write zeros on their owned nodes.
+template <typename T>
 __global__ void __launch_bounds__(kBlock)
 k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0, int sub,
               const double* __restrict__ lamx, const double* __restrict__ lamy,
@@ -147,34 +270,6 @@ k_modal_sweep(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0,
   }
   const double d = g.sigma + lamy[q] + lamx[p];
   const double invd = 1.0 / d;
-  if constexpr (REG) {
-    // Sweeps of at most kRegSteps nodes: every r'_n of the subdomain is loaded (and corrected
-    // by the coarse part) before the recurrences, so the loads are in flight together; the
-    // one register array then holds y_n, then x_n, which are stored after the adjoint sweep.
-    const int cnt = rg.hi - rg.lo + 1;
-    double v[kRegSteps];
-#pragma unroll
-    for (int i = 0; i < kRegSteps; ++i)
-      v[i] = i < cnt ? rprime_at(g, rhat, c0, sub, d, MM, m, rg.lo + i) : 0.0;
-    double y = 0.0;
-#pragma unroll
-    for (int i = 0; i < kRegSteps; ++i)
-      if (i < cnt) {
-        y = (v[i] + y) * invd;
-        v[i] = y;
-      }
-    double x = 0.0;
-#pragma unroll
-    for (int i = kRegSteps - 1; i >= 0; --i)
-      if (i < cnt) {
-        x = (g.h * v[i] + x) * invd;
-        v[i] = x;
-      }
-#pragma unroll
-    for (int i = 0; i < kRegSteps; ++i)
-      if (i < cnt) put_out(g, rg, c0, MM, m, s, rg.lo + i, v[i], zhat, ext);
-    return;
-  }
   double* ysc = yscratch + ((long long)s * g.L) * MM + m;
   // forward sweep over the subdomain's nodes (zero state before the first)
   double y = 0.0;
@@ -292,6 +387,32 @@ k_modal_prolong_add(Geom g, const double* __restrict__ c0, double* __restrict__ 
   for (int n = 1; n <= g.nt; ++n) zhat[(long long)(n - 1) * MM + m] += chat_at(g, c0, MM, m, n);
 }
 
+template <typename T, int R>
+void reg_sweep_r(int W, dim3 grid, hipStream_t s, const Geom& g, const T* rhat, const double* c0,
+                 int sub, const double* lamx, const double* lamy, T* zhat, double* ext) {
+  if (W == 0)
+    hipLaunchKernelGGL((k_modal_sweep_reg<T, R, 0>), grid, dim3(kBlock), 0, s, g, rhat, c0, sub,
+                       lamx, lamy, zhat, ext);
+  else if (W == 3)
+    hipLaunchKernelGGL((k_modal_sweep_reg<T, R, 3>), grid, dim3(kBlock), 0, s, g, rhat, c0, sub,
+                       lamx, lamy, zhat, ext);
+  else
+    hipLaunchKernelGGL((k_modal_sweep_reg<T, R, 5>), grid, dim3(kBlock), 0, s, g, rhat, c0, sub,
+                       lamx, lamy, zhat, ext);
+}
+
+template <typename T>
+void reg_sweep(int R, int W, dim3 grid, hipStream_t s, const Geom& g, const T* rhat,
+               const double* c0, int sub, const double* lamx, const double* lamy, T* zhat,
+               double* ext) {
+  if (R == 12)
+    reg_sweep_r<T, 12>(W, grid, s, g, rhat, c0, sub, lamx, lamy, zhat, ext);
+  else if (R == 24)
+    reg_sweep_r<T, 24>(W, grid, s, g, rhat, c0, sub, lamx, lamy, zhat, ext);
+  else
+    reg_sweep_r<T, 32>(W, grid, s, g, rhat, c0, sub, lamx, lamy, zhat, ext);
+}
+
 template <typename T>
 int modal_t(const Geom& g, const void* rhat, const double* c0, int sub, const double* lamx,
             const double* lamy, double* yscratch, void* zhat, double* ext, hipStream_t s) {
@@ -302,19 +423,32 @@ int modal_t(const Geom& g, const void* rhat, const double* c0, int sub, const do
     hipLaunchKernelGGL(k_modal_exact, grid, dim3(kBlock), 0, s, g,
                        static_cast<const double*>(rhat), c0, sub, lamx, lamy, yscratch,
                        static_cast<double*>(zhat), ext);
-  else if (g.L <= kRegSteps)
-    hipLaunchKernelGGL((k_modal_sweep<T, true>), grid, dim3(kBlock), 0, s, g,
+  else if (g.L <= kRegSteps) {
+    if (MM % kBlock) return set_error(KKTDD_EINVAL, "padded mode count is not a multiple of 256");
+    const int W = !c0 ? 0 : (g.delta < g.k ? 3 : 5);
+    const int R = g.L <= 12 ? 12 : (g.L <= 24 ? 24 : 32);
+    reg_sweep<T>(R, W, grid, s, g, static_cast<const T*>(rhat), c0, sub, lamx, lamy,
+                 static_cast<T*>(zhat), ext);
+  } else {
+    hipLaunchKernelGGL((k_modal_sweep<T>), grid, dim3(kBlock), 0, s, g,
                        static_cast<const T*>(rhat), c0, sub, lamx, lamy, yscratch,
                        static_cast<T*>(zhat), ext);
-  else
-    hipLaunchKernelGGL((k_modal_sweep<T, false>), grid, dim3(kBlock), 0, s, g,
-                       static_cast<const T*>(rhat), c0, sub, lamx, lamy, yscratch,
-                       static_cast<T*>(zhat), ext);
+  }
   KKT_HIP(hipGetLastError());
   // read r_hat over the subdomain nodes, write z_hat once
   const double el = sizeof(T);
   prof_end(KKTDD_K_COARSE, s, el * MM * ((double)g.nd * g.L + g.nt), 0.0);
   return 0;
+}
+
+template <typename T>
+void restrict_t(int R, dim3 grid, hipStream_t s, const Geom& g, const T* rhat, double* r0) {
+  if (R == 16)
+    hipLaunchKernelGGL((k_modal_restrict<T, 16>), grid, dim3(kBlock), 0, s, g, rhat, r0);
+  else if (R == kRegSteps)
+    hipLaunchKernelGGL((k_modal_restrict<T, kRegSteps>), grid, dim3(kBlock), 0, s, g, rhat, r0);
+  else
+    hipLaunchKernelGGL((k_modal_restrict<T, 0>), grid, dim3(kBlock), 0, s, g, rhat, r0);
 }
 
 }  // namespace
@@ -324,12 +458,11 @@ int launch_modal_restrict(const Geom& g, int precision, const void* rhat, double
   const long long MM = g.padded();
   const dim3 grid((unsigned)((MM + kBlock - 1) / kBlock), g.nd);
   prof_begin(KKTDD_K_COARSE, s);
+  const int R = g.k <= 16 ? 16 : (g.k <= kRegSteps ? kRegSteps : 0);
   if (precision != KKTDD_FP64)
-    hipLaunchKernelGGL((k_modal_restrict<float>), grid, dim3(kBlock), 0, s, g,
-                       static_cast<const float*>(rhat), r0);
+    restrict_t<float>(R, grid, s, g, static_cast<const float*>(rhat), r0);
   else
-    hipLaunchKernelGGL((k_modal_restrict<double>), grid, dim3(kBlock), 0, s, g,
-                       static_cast<const double*>(rhat), r0);
+    restrict_t<double>(R, grid, s, g, static_cast<const double*>(rhat), r0);
   KKT_HIP(hipGetLastError());
   prof_end(KKTDD_K_COARSE, s, (precision != KKTDD_FP64 ? 4.0 : 8.0) * MM * g.nt + 8.0 * MM * g.nc, 0.0);
   return 0;
