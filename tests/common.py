@@ -47,7 +47,8 @@ def relerr_blocks_2norm(a, b):
 
 
 # Operator-level parity cases: ragged extents (padding inside the last tile), the degenerate
-# one-node problem, full tiles with overlap = k, the tiny32 workload, and long subdomains.
+# one-node problem, full tiles with overlap = k, the tiny32 workload, long subdomains, and
+# sweeps of 22 and 32 nodes.
 CASES = {
     "tiny_ragged": wl.problem(nx=6, ny=5, nt=8, Lx=1.0, Ly=2.0, nu=0.7, omega=1e-2, n_sub=4, overlap=1, coarse=2),
     "ragged_tiles": wl.problem(nx=37, ny=21, nt=12, Lx=1.3, Ly=0.7, nu=0.3, omega=1e-3, n_sub=3, overlap=2, coarse=2),
@@ -56,5 +57,10 @@ CASES = {
                                        coarse=1),
     "tiny32": wl.config("tiny32")[0],
     "long_subdomains": wl.problem(nx=10, ny=12, nt=80, Lx=1.0, Ly=2.0, nu=1.0, omega=1e-2, n_sub=2, overlap=1,
+                                  coarse=2),
+    # sweeps of 22 and 32 nodes (the longer register forms of the mode-space sweep), the
+    # second with overlap = k
+    "reg24": wl.problem(nx=9, ny=7, nt=80, Lx=1.0, Ly=0.8, nu=0.4, omega=1e-3, n_sub=4, overlap=2, coarse=2),
+    "reg32_overlap_k": wl.problem(nx=7, ny=8, nt=64, Lx=0.9, Ly=1.1, nu=1.3, omega=1e-2, n_sub=4, overlap=16,
                                   coarse=2),
 }

@@ -87,7 +87,8 @@ def test_spatial_solve_tile_shapes(nx, ny, precision, tol):
 
 @pytest.mark.parametrize("sweep", ["step", "modal"])
 @pytest.mark.parametrize("coarse", [0, 1, 2])
-@pytest.mark.parametrize("name", ["tiny_ragged", "ragged_tiles", "full_tiles_overlap_k", "tiny32", "long_subdomains"])
+@pytest.mark.parametrize("name", ["tiny_ragged", "ragged_tiles", "full_tiles_overlap_k", "tiny32", "long_subdomains",
+                                  "reg24", "reg32_overlap_k"])
 def test_precond_matches_oracle(name, coarse, sweep):
     params = dict(CASES[name], coarse=coarse)
     p = Problem(**params).validate()

@@ -31,6 +31,11 @@ BASES = {
     "long": wl.problem(nx=10, ny=12, nt=80, Lx=1.0, Ly=2.0, nu=1.0, omega=1e-2, n_sub=2, overlap=3, coarse=2),
     # one step per subdomain with the largest overlap
     "k1": wl.problem(nx=5, ny=4, nt=6, nu=0.5, omega=1e-1, n_sub=6, overlap=1, coarse=1),
+    # register sweeps of 27 (30 with overlap on both sides) and 24 nodes, the second with
+    # overlap = k
+    "reg32": wl.problem(nx=7, ny=6, nt=96, Lx=1.0, Ly=1.2, nu=0.6, omega=1e-2, n_sub=4, overlap=3, coarse=2),
+    "overlap_k24": wl.problem(nx=6, ny=7, nt=48, Lx=1.0, Ly=1.0, nu=0.9, omega=1e-3, n_sub=4, overlap=12,
+                              coarse=2),
 }
 VARIANTS = {
     "both": dict(overlap_side="both"),
