@@ -642,9 +642,30 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   const int first = s * g.k + 1 - g.delta;
 
   // Right-hand-side operands of b at both points of every pair, fetched before GEMM1 so their
-  // latency hides behind it (after it where registers are capped).
+  // latency hides behind it (after it where registers are capped).  With at most 8 pairs per
+  // thread the source is chosen once per launch and every lane loads all of its pairs
+  // unconditionally (rows and columns past the interior clamped to the last interior point,
+  // their values replaced by zero), so the loads are in flight together; with more pairs that
+  // form would keep every address live and spill, so the loads stay per pair.
+  constexpr bool kBatchPre = RB * NPR <= 8;
   T pre[RB][NPR][2];
-  auto load_pre = [&]() {
+  auto fill_pre = [&](auto base, long long rstride, double isc) {
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+      for (int i = 0; i < NPR; ++i) {
+        const int e = threadIdx.x + i * nthr;
+        const int r = e / Hx, k = e - r * Hx;
+        const int row = row0 + rr * 16 + r;
+        const bool live = row < g.my && k < Ax;
+        const int kc = k < Ax ? k : Ax - 1;
+        const auto* src = base + (long long)(row < g.my ? row : g.my - 1) * rstride;
+        const auto x1 = src[kc], x2 = src[mx - 1 - kc];
+        pre[rr][i][0] = live ? (T)(isc * x1) : (T)0;
+        pre[rr][i][1] = live ? (T)(isc * x2) : (T)0;
+      }
+  };
+  auto load_pre_each = [&]() {
     if (a.b_mode == B_RPRIME_PLUS_Y || a.b_mode == B_H_YBUF_PLUS_Y || a.b_mode == B_INPUT) {
       const int bnode = first + a.b_step;
       const double isc = (a.b_mode == B_INPUT && a.in_scale) ? *a.in_scale : 1.0;
@@ -687,6 +708,32 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
           pre[rr][i][1] = v2;
         }
     }
+  };
+  auto load_pre = [&]() {
+    if constexpr (!kBatchPre) {
+      load_pre_each();
+      return;
+    }
+    const bool from_r = a.b_mode == B_RPRIME_PLUS_Y, from_y = a.b_mode == B_H_YBUF_PLUS_Y;
+    if (!from_r && !from_y && a.b_mode != B_INPUT) return;
+    const int bnode = first + a.b_step;
+    if (from_r && bnode < 1) {
+#pragma unroll
+      for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+        for (int i = 0; i < NPR; ++i) pre[rr][i][0] = pre[rr][i][1] = (T)0;
+      return;
+    }
+    if (from_y) {
+      fill_pre(a.ybuf_in + s * a.ybuf_stride, Mx, 1.0);
+      return;
+    }
+    // r' of the node (B_RPRIME_PLUS_Y) or input slice s (B_INPUT); float32 input is never scaled
+    const long long o = from_r ? (long long)(bnode - 1) * g.nxy : (long long)s * g.nxy;
+    if (a.rin32)
+      fill_pre(a.rin32 + o, mx, 1.0);
+    else
+      fill_pre(a.rin + o, mx, (!from_r && a.in_scale) ? *a.in_scale : 1.0);
   };
   if constexpr (!kTwo) load_pre();
 
@@ -732,51 +779,99 @@ k_rows(Geom g, RowArgs<typename Eng::data_t> a) {
   const bool owned = a.g1_step >= g.delta;
   const int node = first + a.g1_step;
   const T hT = (T)g.h;
-  auto store_y = [&](int row, int col, T v) {
+  // Field output with the prolonged coarse part: OUT_PLAIN slice s is time node s+1, OUT_OWNED
+  // writes node `node`; both add c0 of the owning subdomain cs times (1, phi).  With at most 8
+  // pairs per thread the coarse values of a group of GP pairs are loaded before the group's
+  // stores, unconditionally (clamped like the right-hand side), so they are in flight
+  // together; wider shapes read them per point (the grouped form spills there).
+  const bool out_plain = a.out_mode == OUT_PLAIN, out_owned = a.out_mode == OUT_OWNED && owned;
+  const bool add_c = a.g1_in && a.c0 && (out_plain || out_owned);
+  const int cs = out_plain ? s / g.k : s;
+  const double cphi = -1.0 + 2.0 * (double)((out_plain ? s + 1 : node) - cs * g.k) / g.k;
+  const double* cb = a.c0 ? a.c0 + (long long)(g.nb * cs) * g.nxy : nullptr;
+  const long long o1 = g.nb == 2 ? g.nxy : 0;   // second slot (the first again with nb = 1)
+  auto store_y = [&](int row, int col, T v, double c_0, double c_1) {
     if (a.ystore) a.ystore[s * a.ystore_stride + (long long)row * Mx + col] = v;
     const long long pt = (long long)row * mx + col;
-    if (a.out_mode == OUT_PLAIN) {
+    if (out_plain || out_owned) {
       double val = (double)v;
-      if (a.c0) {   // slice s is time-node s+1 of a field: add the prolonged coarse part
-        const int n = s + 1, sd = s / g.k;
-        const double* c = a.c0 + (long long)(g.nb * sd) * g.nxy + pt;
-        val += c[0];
-        if (g.nb == 2) val += (-1.0 + 2.0 * (double)(n - sd * g.k) / g.k) * c[g.nxy];
+      if (add_c) {
+        val += c_0;
+        if (g.nb == 2) val += cphi * c_1;
       }
-      a.out64[(long long)s * g.nxy + pt] = val;
-    } else if (a.out_mode == OUT_OWNED && owned) {
-      double val = (double)v;
-      if (a.c0) {
-        const double* c = a.c0 + (long long)(g.nb * s) * g.nxy + pt;
-        val += c[0];
-        if (g.nb == 2) val += (-1.0 + 2.0 * (double)(node - s * g.k) / g.k) * c[g.nxy];
-      }
-      a.out64[(long long)(node - 1) * g.nxy + pt] = val;
+      a.out64[(out_plain ? (long long)s : (long long)(node - 1)) * g.nxy + pt] = val;
     }
   };
   T yv[RB][NPR][2];
+  if constexpr (kBatchPre) {
+    constexpr int GP = NPR % 4 == 0 ? 4 : 2;
 #pragma unroll
-  for (int rr = 0; rr < RB; ++rr)
+    for (int rr = 0; rr < RB; ++rr)
 #pragma unroll
-    for (int i = 0; i < NPR; ++i) {
-      const int e = threadIdx.x + i * nthr;
-      const int r = e / Hx, k = e - r * Hx;
-      const int row = row0 + rr * 16 + r;
-      const int c2 = mx - 1 - k;
-      T y1 = 0, y2 = 0;
-      if (a.g1_in) {
-        const T* cr = comb + (rr * 16 + r) * ldc;
-        const T E = cr[k], O = cr[Hx + k];
-        y1 = E + O;
-        y2 = E - O;
-        if (k < Ax && row < g.my) {
-          store_y(row, k, y1);
-          if (k != c2) store_y(row, c2, y2);
+      for (int i0 = 0; i0 < NPR; i0 += GP) {
+        double cv[GP][4];
+        if (add_c) {
+#pragma unroll
+          for (int q = 0; q < GP; ++q) {
+            const int e = threadIdx.x + (i0 + q) * nthr;
+            const int r = e / Hx, k = e - r * Hx;
+            const int row = row0 + rr * 16 + r;
+            const int kc = k < Ax ? k : Ax - 1;
+            const double* c = cb + (long long)(row < g.my ? row : g.my - 1) * mx;
+            cv[q][0] = c[kc];
+            cv[q][1] = c[o1 + kc];
+            cv[q][2] = c[mx - 1 - kc];
+            cv[q][3] = c[o1 + mx - 1 - kc];
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < GP; ++q) {
+          const int i = i0 + q;
+          const int e = threadIdx.x + i * nthr;
+          const int r = e / Hx, k = e - r * Hx;
+          const int row = row0 + rr * 16 + r;
+          const int c2 = mx - 1 - k;
+          T y1 = 0, y2 = 0;
+          if (a.g1_in) {
+            const T* cr = comb + (rr * 16 + r) * ldc;
+            const T E = cr[k], O = cr[Hx + k];
+            y1 = E + O;
+            y2 = E - O;
+            if (k < Ax && row < g.my) {
+              store_y(row, k, y1, cv[q][0], cv[q][1]);
+              if (k != c2) store_y(row, c2, y2, cv[q][2], cv[q][3]);
+            }
+          }
+          yv[rr][i][0] = y1;
+          yv[rr][i][1] = y2;
         }
       }
-      yv[rr][i][0] = y1;
-      yv[rr][i][1] = y2;
-    }
+  } else {
+    // per point: the coarse values are read where they are added
+#pragma unroll
+    for (int rr = 0; rr < RB; ++rr)
+#pragma unroll
+      for (int i = 0; i < NPR; ++i) {
+        const int e = threadIdx.x + i * nthr;
+        const int r = e / Hx, k = e - r * Hx;
+        const int row = row0 + rr * 16 + r;
+        const int c2 = mx - 1 - k;
+        T y1 = 0, y2 = 0;
+        if (a.g1_in) {
+          const T* cr = comb + (rr * 16 + r) * ldc;
+          const T E = cr[k], O = cr[Hx + k];
+          y1 = E + O;
+          y2 = E - O;
+          if (k < Ax && row < g.my) {
+            const double* c = add_c ? cb + (long long)row * mx : nullptr;
+            store_y(row, k, y1, add_c ? c[k] : 0.0, add_c ? c[o1 + k] : 0.0);
+            if (k != c2) store_y(row, c2, y2, add_c ? c[c2] : 0.0, add_c ? c[o1 + c2] : 0.0);
+          }
+        }
+        yv[rr][i][0] = y1;
+        yv[rr][i][1] = y2;
+      }
+  }
   if (!form_b) return;
   if constexpr (kTwo) load_pre();
   if constexpr (!Eng::kCombInPlace) __syncthreads();   // combine values read before the operand is written
