@@ -91,7 +91,7 @@ DESCRIPTIONS = {
 # (traffic null).
 TRAFFIC = {"grid128": {"arnoldi": 496.85e6},
            "grid256": {"arnoldi": 8900.26e6},
-           "grid512": {"arnoldi": 34507.54e6, "matvec": 29346.3e6, "sweeps": 1139.16e6}}
+           "grid512": {"arnoldi": 34507.54e6, "matvec": 29346.3e6, "sweeps": 1143.31e6}}
 
 
 def progress(msg):
