@@ -130,7 +130,7 @@ __device__ inline void put_out(const Geom& g, const Range& rg, const double* __r
   }
 }
 
-// Lane i of a wave reads the value that lane `lane` holds (wave-uniform result).
+// Every lane of the wave gets the value that lane `lane` holds (a wave-uniform result).
 __device__ inline double lane_value(double v, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
