@@ -155,12 +155,13 @@ __device__ inline double pick(const double (&a)[W], int j) {
 //     W = 3 when delta < k, 5 when delta = k.
 // The owner slot and linear basis value of node lo-1+i sit in lane i of every wave (all lanes
 // active) and are read back as wave-uniform values, so c_hat of a node is one select chain
-// and one multiply-add.  `sub` subtracts S_hat c_hat / h from r_hat (coarse level first);
-// with W > 0 the output adds c_hat on owned nodes either way.  Padded modes compute on an
-// in-range eigenvalue entry and write zeros.  The padded mode count is a multiple of the
-// workgroup size, so every thread has a mode.
+// and one multiply-add, recomputed where it is used rather than held through the sweeps
+// (with R <= 24 the kernel then fits four waves per SIMD).  `sub` subtracts S_hat c_hat / h
+// from r_hat (coarse level first); with W > 0 the output adds c_hat on owned nodes either
+// way.  Padded modes compute on an in-range eigenvalue entry and write zeros.  The padded mode
+// count is a multiple of the workgroup size, so every thread has a mode.
 template <typename T, int R, int W>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock, (W > 0 && R <= 24) ? 4 : 1)
 k_modal_sweep_reg(Geom g, const T* __restrict__ rhat, const double* __restrict__ c0, int sub,
                   const double* __restrict__ lamx, const double* __restrict__ lamy,
                   T* __restrict__ zhat, double* __restrict__ ext) {
@@ -188,9 +189,9 @@ k_modal_sweep_reg(Geom g, const T* __restrict__ rhat, const double* __restrict__
 #pragma unroll
   for (int i = 0; i < R; ++i)
     v[i] = (double)rhat[(long long)(rg.lo - 1 + (i < cnt ? i : cnt - 1)) * MM + m];
-  double ch[R + 2];
+  // c_hat of node lo-1+i, recomputed where it is used (the same operations every time)
+  double ca[W > 0 ? W : 1], cb[W > 0 ? W : 1];
   if constexpr (W > 0) {
-    double ca[W], cb[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) {
       int o = s - W / 2 + j;
@@ -198,29 +199,34 @@ k_modal_sweep_reg(Geom g, const T* __restrict__ rhat, const double* __restrict__
       ca[j] = c0[(long long)(g.nb * o) * MM + m];
       cb[j] = c0[(long long)(g.nb * o + g.nb - 1) * MM + m];
     }
-    const bool lin = g.nb == 2;
-#pragma unroll
-    for (int i = 0; i < R + 2; ++i) {
+  }
+  const bool lin = g.nb == 2;
+  auto chat = [&](int i) -> double {
+    if constexpr (W > 0) {
       const int j = __builtin_amdgcn_readlane(tslot, i);
       const double ph = lane_value(tphi, i);
       const double a = pick<W>(ca, j);
       const double c = lin ? a + ph * pick<W>(cb, j) : a;
-      ch[i] = j < 0 ? 0.0 : c;
+      return j < 0 ? 0.0 : c;
+    } else {
+      return 0.0;
     }
+  };
+  if constexpr (W > 0) {
     if (sub) {
+      double cm = chat(0), cn = chat(1);
 #pragma unroll
       for (int i = 0; i < R; ++i)
         if (i < cnt) {
           // (S_hat c)^n h = (d^2 + [n>=2]) c^n - d c^{n+1} - [n>=2] d c^{n-1}, n = lo + i
-          const double cn = ch[i + 1];
-          double sc = d * d * cn - d * ch[i + 2];
-          if (rg.lo + i >= 2) sc += cn - d * ch[i];
+          const double cp = chat(i + 2);
+          double sc = d * d * cn - d * cp;
+          if (rg.lo + i >= 2) sc += cn - d * cm;
           v[i] -= sc / g.h;
+          cm = cn;
+          cn = cp;
         }
     }
-  } else {
-#pragma unroll
-    for (int i = 0; i < R + 2; ++i) ch[i] = 0.0;
   }
   double y = 0.0;
 #pragma unroll
@@ -242,7 +248,7 @@ k_modal_sweep_reg(Geom g, const T* __restrict__ rhat, const double* __restrict__
     if (i < cnt) {
       const int n = rg.lo + i;
       if (n >= rg.own_lo && n <= rg.own_hi) {
-        zhat[(long long)(n - 1) * MM + m] = pad ? (T)0 : (T)(ch[i + 1] + v[i]);
+        zhat[(long long)(n - 1) * MM + m] = pad ? (T)0 : (T)(chat(i + 1) + v[i]);
       } else if (ext && !pad) {
         const int slot = n < rg.own_lo ? n - rg.first : g.delta + (n - rg.own_hi - 1);
         ext[((long long)s * E + slot) * MM + m] = v[i];
